@@ -1,0 +1,24 @@
+"""CPU FP64 oracle for cell-wise matrix-free Q_k finite elements.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package imports this
+package; only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
+leg of ``bench.py`` may use it.  It is written from the definitions in the
+paper "Coalesced Matrix-Free Geometric Multigrid on Persistent Cell-Wise
+Storage" (Wichrowski): it assembles sparse global matrices and dense local
+patch matrices and inverts them directly, so that every fast route taken by
+the HIP library (sum factorization, DSS cascades, fast diagonalization,
+cell-wise transfers, primal-dual CG) can be checked against a plain
+definition.  It shares no code with the HIP path.
+
+Modules
+-------
+basis      1D Gauss-Lobatto Lagrange basis, 1D mass/stiffness, 1D transfers
+mesh       structured mesh indexing, the gather operator G, valence
+operators  element matrices, CSR assembly of A_CG, cell-wise apply, DSS
+patch      vertex patches, dense patch matrices and their inverses
+geometry   deformed Q_k geometry, coefficient field, general element matrices
+kron       Kronecker form of the Cartesian operator and its exact solver
+multigrid  assembled hierarchy, classical smoothers, V-cycle, PCG
+sepfit     best separable (Kronecker-sum) fit of patch matrices
+mlp        reference MLP forward / manual backward / Adam step
+"""

@@ -1,0 +1,192 @@
+"""Pins for the oracle's patch inverse, transfers, V-cycle and PCG."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.basis import gll_nodes, mass_1d, stiffness_1d
+from oracle.kron import KroneckerOperator
+from oracle.mesh import StructuredMesh
+from oracle.multigrid import (Hierarchy, make_chebyshev_smoother, make_jacobi_smoother, pcg,
+                              vcycle)
+from oracle.operators import assemble_csr, dirichlet_block, element_matrix_cartesian
+from oracle.patch import (patch_dof_indices, patch_inverse_cellwise, patch_matrices,
+                          patch_membership_count)
+from synthetic_inputs import uniform
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_convergence.json")
+
+
+def _mesh_and_A(dim, k, n):
+    m = StructuredMesh(dim, k, n)
+    return m, assemble_csr(m, element_matrix_cartesian(dim, k, m.h))
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (3, 3)])
+def test_single_patch_is_exact_inverse(dim, k):
+    """n = 2: the one patch covers every interior DoF, so the patch inverse is A_II^{-1}."""
+    m, A = _mesh_and_A(dim, k, 2)
+    r = uniform(m.n_cellwise, seed=11).reshape(m.n_cells, m.n_local)
+    z = patch_inverse_cellwise(A, m, r)
+    bmask = m.boundary_mask_global()
+    rg = m.assemble(r)
+    ko = KroneckerOperator(dim, k, 2)
+    u = np.zeros(m.n_global)
+    u[~bmask] = ko.solve(rg[~bmask])
+    assert np.max(np.abs(z - m.gather(u))) < 1e-12 * np.abs(u).max()
+
+
+@pytest.mark.parametrize("dim,k,n", [(2, 2, 4), (3, 2, 3)])
+def test_patch_membership_closed_form(dim, k, n):
+    m, _ = _mesh_and_A(dim, k, n)
+    gc = m.global_coords()
+    cnt = np.ones(m.n_global, dtype=np.int64)
+    for a in range(dim):
+        g = gc[:, a]
+        # vertex v's patch interior is k(v-1) < g < k(v+1) with 1 <= v <= n-1
+        c = np.zeros_like(g)
+        for v in range(1, n):
+            c += (g > k * (v - 1)) & (g < k * (v + 1))
+        cnt *= c
+    assert np.array_equal(patch_membership_count(m), cnt)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 3), (2, 5)])
+def test_cartesian_patch_matrix_is_kronecker_sum(dim, k):
+    """A_p = Kt x Mt (x Mt) + ... with the two-interval 1D patch matrices."""
+    n = 3
+    m, A = _mesh_and_A(dim, k, n)
+    h = m.h
+    B, D = mass_1d(k), stiffness_1d(k)
+    Kt = np.zeros((2 * k + 1, 2 * k + 1))
+    Mt = np.zeros_like(Kt)
+    for e in range(2):
+        s = slice(k * e, k * e + k + 1)
+        Kt[s, s] += D / h
+        Mt[s, s] += h * B
+    Kt, Mt = Kt[1:-1, 1:-1], Mt[1:-1, 1:-1]
+    if dim == 2:
+        Ap = np.kron(Mt, Kt) + np.kron(Kt, Mt)
+    else:
+        Ap = np.kron(Mt, np.kron(Mt, Kt)) + np.kron(Mt, np.kron(Kt, Mt)) + np.kron(Kt, np.kron(Mt, Mt))
+    P = patch_matrices(A, m)
+    for p in range(P.shape[0]):
+        assert np.max(np.abs(P[p] - Ap)) < 1e-12 * np.abs(Ap).max()
+
+
+def test_patch_inverse_depends_only_on_assembled_residual_and_is_continuous():
+    m, A = _mesh_and_A(3, 2, 3)
+    r = uniform(m.n_cellwise, seed=12).reshape(m.n_cells, m.n_local)
+    z = patch_inverse_cellwise(A, m, r)
+    # a perturbation with G^T v = 0: move mass between the copies of each DoF
+    v = uniform(m.n_cellwise, seed=13).reshape(r.shape)
+    v = v - m.gather(m.assemble(v) / m.valence_global())
+    assert np.max(np.abs(m.assemble(v))) < 1e-14
+    z2 = patch_inverse_cellwise(A, m, r + v)
+    assert np.max(np.abs(z - z2)) < 1e-12
+    # continuous output: every copy of a DoF holds the same value
+    zg = m.assemble(z) / m.valence_global()
+    assert np.max(np.abs(m.gather(zg) - z)) < 1e-14
+    # shared-matrix fast path equals the per-patch loop on the Cartesian mesh
+    z3 = patch_inverse_cellwise(A, m, r, shared=True)
+    assert np.max(np.abs(z - z3)) < 1e-12
+
+
+def test_patch_solves_satisfy_local_systems():
+    m, A = _mesh_and_A(2, 3, 4)
+    idx = patch_dof_indices(m)
+    P = patch_matrices(A, m)
+    rg = uniform(m.n_global, seed=14)
+    for p in range(P.shape[0]):
+        w = sla.solve(P[p], rg[idx[p]], assume_a="pos")
+        assert np.linalg.norm(P[p] @ w - rg[idx[p]]) < 1e-12 * np.linalg.norm(rg[idx[p]])
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (3, 3), (2, 4)])
+def test_transfer_galerkin_property_and_polynomial_reproduction(dim, k):
+    h = Hierarchy(dim, k, 4)
+    for l in range(1, h.L + 1):
+        P = h.P[l - 1]
+        Af, Ac = h.levels[l].A, h.levels[l - 1].A
+        G = (P.T @ Af @ P).toarray()
+        assert np.max(np.abs(G - Ac.toarray())) < 1e-12 * abs(Ac).max()
+    # interpolation reproduces a polynomial that vanishes on the boundary: x(1-x) y(1-y) (z(1-z))
+    xi = gll_nodes(k)
+
+    def nodal(n):
+        line = np.empty(k * n + 1)
+        for e in range(n):
+            line[k * e:k * e + k + 1] = (e + xi) / n
+        m = StructuredMesh(dim, k, n)
+        X = line[m.global_coords()]
+        u = np.prod(X * (1 - X), axis=1)
+        return u[~m.boundary_mask_global()]
+
+    if k >= 2:
+        assert np.max(np.abs(h.P[-1] @ nodal(2) - nodal(4))) < 1e-14
+
+
+def _contraction(h, M, A, cycles=12, seed=21):
+    e = uniform(A.shape[0], seed=seed)
+    nrm = lambda v: np.sqrt(v @ (A @ v))
+    rates = []
+    for _ in range(cycles):
+        e_new = e - M(A @ e)
+        rates.append(nrm(e_new) / nrm(e))
+        e = e_new
+    return rates[-1]
+
+
+@pytest.mark.slow
+def test_jacobi_vcycle_contraction_against_paper():
+    """Paper, Sec. 7.1: contraction 0.36 (p=2) to 0.49 (p=4) per V-cycle, omega = 0.7.
+
+    The paper's 'two smoothing steps' is read as nu1 = nu2 = 2; the contraction
+    of the classical V-cycle must then be no worse than the paper's figures and
+    must grow with p (a point smoother is not p-robust, Sec. 1).
+    """
+    gold = json.load(open(GOLDEN))["vcycle_contraction_uniform"]
+    rates = []
+    for k in (2, 3):
+        h = Hierarchy(3, k, 8)
+        sm = make_jacobi_smoother(0.7, 2, 2)
+        M = lambda r: vcycle(h, r, sm)
+        rates.append(_contraction(h, M, h.levels[-1].A, cycles=20))
+    assert 0.1 < rates[0] < gold["p2"], rates
+    assert rates[0] < rates[1] < gold["p4"], rates
+
+
+@pytest.mark.slow
+def test_pcg_with_vcycle_reaches_exact_discrete_solution():
+    k, n = 3, 8
+    h = Hierarchy(3, k, n)
+    A = h.levels[-1].A
+    ko = KroneckerOperator(3, k, n)
+    b = uniform(A.shape[0], seed=22)
+    sm = make_jacobi_smoother(0.7, 2, 2)
+    x, it, hist = pcg(A, b, lambda r: vcycle(h, r, sm), tol=1e-10)
+    xe = ko.solve(b)
+    assert hist[-1] <= 1e-10
+    assert it <= 2 * json.load(open(GOLDEN))["cg_iterations_cube"]["p3"]
+    assert np.linalg.norm(x - xe) / np.linalg.norm(xe) < 1e-7
+
+
+@pytest.mark.slow
+def test_chebyshev_patch_smoother_vcycle():
+    k, n = 3, 4
+    h = Hierarchy(3, k, n)
+    # exact lambda_max of the patch-preconditioned operator on each level
+    lmax = []
+    for lev in h.levels:
+        if lev.n_int == 0 or lev.mesh.n < 2:
+            lmax.append(1.0)
+            continue
+        A = lev.A.toarray()
+        PA = np.stack([lev.patch_inverse(A[:, j], shared=True) for j in range(A.shape[1])], axis=1)
+        lmax.append(np.max(np.real(np.linalg.eigvals(PA))))
+    sm = make_chebyshev_smoother([1.2 * l for l in lmax], degree=3)
+    M = lambda r: vcycle(h, r, sm)
+    rate = _contraction(h, M, h.levels[-1].A, cycles=8)
+    assert rate < 0.25, rate
