@@ -1,0 +1,238 @@
+"""Benchmark: cell-wise Q_k operator apply + vertex-patch FDM inverse on one MI355X.
+
+One step = fe_apply followed by patch_fdm_inverse on the 3D Q3 64^3 Cartesian
+mesh (193^3 = 7,189,057 unique DoFs, 16.8M cell-wise entries), FP64, inputs
+resident in HBM.  Four independent (x, y, r, z) buffer sets are rotated so
+that the working set exceeds the 256 MB last-level cache.  The headline value
+is unique DoFs per second of whole steps.  Also reported (not part of the
+timed steps): the FP32 step, the Q7 32^3 step, per-kernel durations from HIP
+events on the launch stream, the MG-PCG solves on Q7 32^3 (FP32 Chebyshev
+patch-FDM smoother inside FP64 CG vs the plain FP64 Jacobi-MG solve), and the
+CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-pcg] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GDoF/s apply+patch inverse (Q3/Q7, FP32 vs FP64); PCG s to 1e-10 rel. res."
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-step", action="store_true", help="time the headline step only (for profilers)")
+    return ap.parse_args()
+
+
+def make_inputs(fe, P, dtype, nsets, seed0):
+    import torch
+    from synthetic_inputs import uniform
+    sets = []
+    for i in range(nsets):
+        xg = torch.as_tensor(uniform(P.n_dofs, seed=seed0 + 2 * i), dtype=torch.float64, device="cuda")
+        x64 = P.cellvec(torch.float64)
+        P.gather(xg, x64)
+        x = x64.to(dtype)
+        r = torch.as_tensor(uniform(P.len, seed=seed0 + 2 * i + 1), dtype=dtype, device="cuda")
+        sets.append((x, P.cellvec(dtype), r, P.cellvec(dtype)))
+        del xg, x64
+    return sets
+
+
+def time_steps(P, sets, steps, warmup):
+    import torch
+
+    def step(i):
+        x, y, r, z = sets[i % len(sets)]
+        P.apply(x, y)
+        P.patch_inverse(r, z)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for i in range(steps):
+        step(i)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps   # ms per step
+
+
+def kernel_times(fe, P, sets, reps):
+    """Average duration (ms) of each kernel family over `reps` steps, HIP events on the launch stream."""
+    import torch
+    fe.prof_reset()
+    fe.prof_enable(True)
+    for i in range(reps):
+        x, y, r, z = sets[i % len(sets)]
+        P.apply(x, y)
+        P.patch_inverse(r, z)
+    torch.cuda.synchronize()
+    fe.prof_enable(False)
+    out = {}
+    for name in ("apply", "fdm_patch", "fdm_sum"):
+        c, t = fe.prof_query(name)
+        if c:
+            out[name] = t / c
+    fe.prof_reset()
+    return out
+
+
+def kernel_bytes(P, dt_bytes):
+    """Algorithmic bytes per launch of each kernel family."""
+    k, n = P.degree, P.n
+    m = 2 * k - 1
+    n_patches = (n - 1) ** 3
+    vec = P.len * dt_bytes
+    wbuf = n_patches * m ** 3 * dt_bytes
+    return {"apply": 2 * vec, "fdm_patch": vec + wbuf, "fdm_sum": wbuf + vec}
+
+
+def bench_config(fe, degree, n, dtype, steps, warmup, nsets):
+    import torch
+    P = fe.Problem(3, degree, n, bc=1)
+    sets = make_inputs(fe, P, dtype, nsets, seed0=0)
+    ms = time_steps(P, sets, steps, warmup)
+    kt = kernel_times(fe, P, sets, max(10, steps // 2))
+    kb = kernel_bytes(P, 8 if dtype == torch.float64 else 4)
+    res = {"ms_per_step": ms, "gdofs": P.n_dofs / (ms * 1e-3) / 1e9, "n_dofs": P.n_dofs,
+           "kernel_ms": kt, "kernel_gbs": {k: kb[k] / (v * 1e-3) / 1e9 for k, v in kt.items()}}
+    del sets
+    P.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_pcg(fe):
+    """Q7 32^3, manufactured RHS, tol 1e-10: FP32 Chebyshev(3) patch-FDM MG inside FP64 CG vs FP64 Jacobi MG."""
+    import torch
+    P = fe.Problem(3, 7, 32, bc=1)
+    b = P.cellvec()
+    P.rhs_manufactured(b)
+    out = {}
+    for name, opts in (
+            ("fp32_chebfdm_flexible", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
+                                                      nu_pre=1, nu_post=1, tol=1e-10)),
+            ("fp64_jacobi_plain", fe.default_opts(smoother=fe.SMOOTH_JACOBI, inner=fe.F64, omega=0.7,
+                                                  nu_pre=2, nu_post=2, tol=1e-10, maxit=400))):
+        x = P.cellvec()
+        P.pcg_solve(b, x, opts, raise_on_error=False)     # includes setup
+        x.zero_()
+        rep = P.pcg_solve(b, x, opts, raise_on_error=False)  # timed solve with setup cached
+        out[name] = {"seconds": rep["t_solve"], "iters": rep["iters"], "relres": rep["relres"],
+                     "setup_s": rep["t_setup"], "converged": rep["converged"], "status": rep["status"]}
+        log("pcg %s: %.4f s, %d iters, relres %.2e" % (name, rep["t_solve"], rep["iters"], rep["relres"]))
+    P.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline():
+    """The oracle (numpy/scipy FP64, unmodified) on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle.mesh import StructuredMesh
+    from oracle.operators import apply_cellwise, assemble_csr, element_matrix_cartesian
+    from oracle.patch import patch_inverse_cellwise
+    from synthetic_inputs import uniform
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    k, n = 3, 16
+    m = StructuredMesh(3, k, n)
+    E = element_matrix_cartesian(3, k, m.h)
+    A = assemble_csr(m, E)
+    x = m.gather(uniform(m.n_global, seed=0))
+    r = uniform(m.n_cellwise, seed=1).reshape(m.n_cells, m.n_local)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        apply_cellwise(m, E, x)
+        patch_inverse_cellwise(A, m, r, shared=True)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0 or reps >= 50:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": m.n_global / dt / 1e9, "unit": "GDoF/s", "cores": cores, "kind": "oracle",
+            "sample": "Q3 16^3 (%d DoFs) apply + patch inverse, FP64, %d repetitions in %.1f s" %
+                      (m.n_global, reps, dt * reps)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_2607_03413_amd import fe
+
+    log("Q3 64^3 FP64 step")
+    main64 = bench_config(fe, 3, 64, torch.float64, args.steps, args.warmup, nsets=4)
+    dom = max(main64["kernel_ms"], key=lambda k: main64["kernel_ms"][k])
+    kb = kernel_bytes(fe.Problem(3, 3, 2, bc=1), 8)  # shapes only
+    P64 = None
+    if args.only_step:
+        print(json.dumps(main64))
+        return
+    log("Q3 64^3 FP32 step")
+    main32 = bench_config(fe, 3, 64, torch.float32, args.steps, args.warmup, nsets=4)
+    log("Q7 32^3 FP64 / FP32 steps")
+    q7_64 = bench_config(fe, 7, 32, torch.float64, max(10, args.steps // 2), args.warmup, nsets=4)
+    q7_32 = bench_config(fe, 7, 32, torch.float32, max(10, args.steps // 2), args.warmup, nsets=4)
+    pcg = None if args.no_pcg else bench_pcg(fe)
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    # roofline entry for the dominant kernel of the headline step
+    k_ms = main64["kernel_ms"][dom]
+    P = fe.Problem(3, 3, 64, bc=1)
+    bytes_dom = kernel_bytes(P, 8)[dom]
+    P.close()
+    achieved = bytes_dom / (k_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(k_ms, 5), "algorithmic_bytes": bytes_dom}
+    line = {
+        "metric": METRIC, "value": round(main64["gdofs"], 4), "unit": "GDoF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main64["ms_per_step"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3D Poisson Q3 64^3 Cartesian, fe_apply + patch_fdm_inverse per step",
+                   "unique_dofs": main64["n_dofs"], "precision": "fp64", "buffer_sets": 4},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp32": {"value": round(main32["gdofs"], 4), "ms_per_step": round(main32["ms_per_step"], 5),
+                 "kernel_ms": main32["kernel_ms"], "kernel_gbs": main32["kernel_gbs"]},
+        "fp64_kernels": {"kernel_ms": main64["kernel_ms"], "kernel_gbs": main64["kernel_gbs"]},
+        "q7_32cubed": {"fp64": {"value": round(q7_64["gdofs"], 4), "kernel_ms": q7_64["kernel_ms"]},
+                       "fp32": {"value": round(q7_32["gdofs"], 4), "kernel_ms": q7_32["kernel_ms"]},
+                       "unique_dofs": q7_64["n_dofs"]},
+        "pcg_q7_32cubed": pcg,
+    }
+    del kb, P64
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

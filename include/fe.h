@@ -1,0 +1,235 @@
+/*
+ * fe.h - C ABI of the MI355X cell-wise matrix-free Q_k finite element library.
+ *
+ * Method: W. Wichrowski, "Coalesced Matrix-Free Geometric Multigrid on
+ * Persistent Cell-Wise Storage".  Every vector lives in redundant cell-wise
+ * storage (Sec. 2.1): each cell keeps its own copy of all (k+1)^d nodal DoFs
+ * it touches.  Primal vectors (iterates, corrections) are continuous: all
+ * copies of a DoF agree.  Dual vectors (residuals, operator outputs) hold
+ * unassembled partial integrals: only the sum of the copies is meaningful.
+ *
+ * Layout of a cell-wise vector (host or device, dtype given per call):
+ *   n_cells blocks of (k+1)^d contiguous values, cell index
+ *   e = cx + n*cy (+ n^2*cz), local index i = ix + K*iy (+ K^2*iz), K = k+1,
+ *   x fastest.  The mesh is the unit square/cube split into n^d equal cells.
+ * Global (assembled) vectors are indexed by node (gx, gy, gz), g = k*c + i,
+ *   on the (k n + 1)^d grid, x fastest.
+ *
+ * Ownership: every pointer argument to a compute call is a DEVICE pointer
+ * owned by the caller (e.g. a torch tensor); the library never frees it.
+ * Buffers must be 16-byte aligned.  The library owns the setup data behind
+ * the fe_problem handle and releases it in fe_problem_destroy.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Compute
+ * calls are asynchronous on that stream unless stated otherwise.  Calls on one
+ * problem handle must not overlap on different streams.
+ *
+ * Errors: every call returns an fe_status and never throws.  On a non-OK
+ * status, fe_last_error() returns a thread-local description.  Output buffers
+ * are left unspecified after an error.
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fe_problem fe_problem;
+
+typedef enum {
+  FE_OK = 0,
+  FE_EINVAL = -1,       /* bad argument: null pointer, misaligned buffer, unsupported (d,k), ... */
+  FE_ENOMEM = -2,       /* a device or host allocation failed */
+  FE_EHIP = -3,         /* a HIP runtime call failed */
+  FE_ENOTCONV = -4,     /* iteration limit reached; x holds the last iterate */
+  FE_EBREAKDOWN = -5,   /* CG breakdown: <p, A p> <= 0 or <r, z> <= 0, or a non-finite value */
+  FE_EUNSUPPORTED = -6  /* valid request that this build does not implement */
+} fe_status;
+
+typedef enum { FE_F64 = 0, FE_F32 = 1 } fe_dtype;
+
+typedef enum { FE_GEOM_CARTESIAN = 0, FE_GEOM_DEFORMED = 1 } fe_geometry;
+
+/* Smooth coefficient field kappa(x) = exp(g(x)),
+ *   g(x) = s * sum_j amp[j] * cos(pi * (m_j . x) + phase[j]),
+ * with s chosen so that max |g| over the quadrature points equals 1
+ * (host arrays, read during fe_problem_create only).  n_modes = 0 means kappa = 1. */
+typedef struct {
+  int n_modes;
+  const int32_t* modes;    /* n_modes x 3, (mx, my, mz) */
+  const double* amp;       /* n_modes */
+  const double* phase;     /* n_modes */
+} fe_coefficient;
+
+typedef struct {
+  int dim;                 /* 2 or 3 */
+  int degree;              /* k, 1..8 */
+  int n;                   /* cells per direction on the finest level */
+  int geometry;            /* fe_geometry */
+  double deform_amp;       /* deformed geometry: x_a += amp * prod_b sin(2 pi x_b), each a */
+  fe_coefficient coef;     /* deformed geometry only; ignored for Cartesian */
+  int bc;                  /* 0: no boundary condition (A 1 = 0); 1: homogeneous Dirichlet */
+  int n_coarse;            /* cells per direction on the coarsest level (0: smallest possible) */
+} fe_problem_desc;
+
+/* Sec. 2 (model problem) and Sec. 3 (hierarchy T_0 < ... < T_L by uniform
+ * bisection).  Builds the level hierarchy and the per-problem constant data
+ * (1D reference matrices, patch eigen-data, geometry for the deformed case)
+ * on the device of `stream`.  Synchronous. */
+fe_status fe_problem_create(const fe_problem_desc* desc, void* stream, fe_problem** out);
+void fe_problem_destroy(fe_problem* prob);
+
+int64_t fe_num_cells(const fe_problem* prob);      /* n^d on the finest level */
+int64_t fe_cellvec_len(const fe_problem* prob);    /* n^d (k+1)^d */
+int64_t fe_num_dofs(const fe_problem* prob);       /* (k n + 1)^d unique DoFs */
+int fe_num_levels(const fe_problem* prob);         /* L + 1 */
+int fe_level_cells_1d(const fe_problem* prob, int level);   /* n_l, level 0 = coarsest */
+
+/* Sec. 2.1: gather G (replicate global coefficients into every cell copy).
+ * x_glob: (k n+1)^d values; x_cell: cell-wise, finest level.  Bit-exact copy. */
+fe_status fe_gather(const fe_problem* prob, const void* x_glob, void* x_cell, fe_dtype dt, void* stream);
+
+/* Sec. 2.1: assembly G^T (sum all cell copies of each global DoF). */
+fe_status fe_assemble(const fe_problem* prob, const void* y_cell, void* y_glob, fe_dtype dt, void* stream);
+
+/* Sec. 4.1 eq. dss_operator (averaging = 0): S v = G G^T v, in place, every
+ * copy receives the sum of all copies.  Sec. 5 eq. averaging_dss
+ * (averaging = 1): S_bar v = G (G^T G)^{-1} G^T v.  Copies are summed in the
+ * order of the axis-split cascade of Algorithm 7 (x pairs, then y, then z),
+ * so the result equals that cascade bit for bit.  `level` selects the mesh
+ * level (-1 = finest). */
+fe_status fe_dss(const fe_problem* prob, int level, void* v_cell, int averaging, fe_dtype dt, void* stream);
+
+/* Sec. 2.1 (cell-wise operator A: V_cell -> V_cell^*) and Sec. 6 (cube:
+ * (D x B x B + B x D x B + B x B x D) det(J) J^-2; deformed: general
+ * cell-wise Laplacian with coefficient).  y = A x cell by cell (dual output,
+ * unassembled).  x should be continuous.  With bc = 1 the boundary copies of
+ * x are treated as zero and the boundary copies of y are set to zero.
+ * x and y must not alias. */
+fe_status fe_apply(const fe_problem* prob, const void* x_cell, void* y_cell, fe_dtype dt, void* stream);
+fe_status fe_apply_level(const fe_problem* prob, int level, const void* x_cell, void* y_cell,
+                         fe_dtype dt, void* stream);
+
+/* Vertex-patch additive Schwarz inverse, an admissible smoother of the form
+ * P = G P_CG G^T (Sec. 2.1 eq. precond_consistency; Sec. 3.3 and Sec. 4.1
+ * name overlapping vertex-patch smoothers as substitutes):
+ *   z = G sum_p R_p^T A_p^{-1} R_p G^T r,
+ * p over the interior mesh vertices, R_p the (2k-1)^d DoFs strictly inside
+ * the 2^d cells around the vertex.  A_p^{-1} is applied by fast
+ * diagonalization with 1D generalized eigenpairs (K S = M S Lambda).
+ *   factors = 0: exact separable factors (Cartesian mesh only),
+ *   factors = 1: per-patch averaged-geometry factors (deformed mesh),
+ *   factors = 2: per-patch learned factors (after fe_mlp_train).
+ * r: dual cell-wise; z: primal cell-wise (continuous, copies bit-identical).
+ * The result depends only on G^T r.  r and z must not alias. */
+fe_status patch_fdm_inverse(const fe_problem* prob, const void* r_cell, void* z_cell, fe_dtype dt,
+                            int factors, void* stream);
+fe_status patch_fdm_inverse_level(const fe_problem* prob, int level, const void* r_cell, void* z_cell,
+                                  fe_dtype dt, int factors, void* stream);
+
+/* Sec. 3.1 Algorithm 2: e_fine += (P_b1 x P_b2 x P_b3) e_coarse on every
+ * child, level `fine_level` >= 1.  Continuous in, continuous out (lemma on
+ * commutativity of prolongation). */
+fe_status fe_prolongate_add(const fe_problem* prob, int fine_level, const void* e_coarse, void* e_fine,
+                            fe_dtype dt, void* stream);
+
+/* Sec. 3.1 Algorithm 3 with the fused residual of Sec. 5:
+ * b_coarse = sum_c (P_b1^T x ...) (b_fine - v_fine)|child c (overwrites b_coarse).
+ * v_fine may be NULL (treated as zero).  Unassembled in, unassembled out. */
+fe_status fe_restrict_residual(const fe_problem* prob, int fine_level, const void* b_fine,
+                               const void* v_fine, void* b_coarse, fe_dtype dt, void* stream);
+
+/* Sec. 5 Algorithm 9, one fused masked Jacobi sweep on `level`:
+ *   v = A u;  u += omega * Dhat^{-1} (b - v);  u = S_bar u,
+ * Dhat^{-1} = valence / assembled diagonal, zero on Dirichlet DoFs.
+ * v is caller scratch (cell-wise, same dtype).  If u_is_zero, v = A u is skipped. */
+fe_status fe_jacobi_sweep(const fe_problem* prob, int level, const void* b, void* u, void* v,
+                          double omega, int u_is_zero, fe_dtype dt, void* stream);
+
+/* Manufactured load vector of the model problem (Sec. 2, eq. poisson):
+ * b_K,i = int_K f phi_i with f = d pi^2 prod_a sin(pi x_a) (mapped through
+ * the geometry, times the coefficient if any), Gauss rule with k+2 points per
+ * direction.  FP64 output, dual cell-wise. */
+fe_status fe_rhs_manufactured(const fe_problem* prob, void* b_cell, void* stream);
+
+/* Energy pairing of Sec. 3.4 eq. energy_measure and friends: local
+ * Euclidean pairing sum_i a_i b_i over the cell-wise vectors (FP64 result,
+ * FP64 accumulation, deterministic).  Synchronous. */
+fe_status fe_dot(const fe_problem* prob, const void* a, const void* b, fe_dtype dt, double* out, void* stream);
+
+/* ||G^T r||_2^2 for a dual cell-wise vector (assembled residual norm), FP64
+ * accumulation.  Synchronous. */
+fe_status fe_assembled_norm2(const fe_problem* prob, const void* r_cell, fe_dtype dt, double* out,
+                             void* stream);
+
+typedef enum { FE_SMOOTH_JACOBI = 0, FE_SMOOTH_CHEB_FDM = 1 } fe_smoother;
+
+typedef struct {
+  double tol;              /* stop when ||G^T r||_2 <= tol * ||G^T b||_2 */
+  int maxit;
+  int nu_pre, nu_post;     /* smoothing sweeps per level */
+  int smoother;            /* fe_smoother */
+  int cheb_degree;         /* Chebyshev degree (smoother = 1) */
+  double cheb_ratio;       /* interval [lmax/ratio, lmax] */
+  double cheb_lmax;        /* > 0: use this lambda_max estimate on every level (tests) */
+  double omega;            /* Jacobi relaxation (smoother = 0) */
+  int inner;               /* fe_dtype of the V-cycle (FE_F32: FP32 preconditioner) */
+  int factors;             /* patch factors for smoother = 1 (see patch_fdm_inverse) */
+  int flexible;            /* 1: Polak-Ribiere beta (recommended with inner = FE_F32) */
+  int precond;             /* 1: V-cycle preconditioner, 0: none (plain CG) */
+} fe_pcg_opts;
+
+typedef struct {
+  int iters;
+  int converged;
+  double relres;           /* ||G^T r||_2 / ||G^T b||_2 at exit */
+  double energy0, energy;  /* <r, z> at start and exit */
+  double t_setup, t_solve; /* seconds (host wall clock, synchronized) */
+} fe_pcg_report;
+
+/* Fill opts with defaults: tol 1e-10, maxit 200, nu 2/2, Jacobi omega 0.7,
+ * Chebyshev degree 3, ratio 20, FP64 inner, standard beta. */
+void fe_pcg_default_opts(fe_pcg_opts* opts);
+
+/* Sec. 4.4: conjugate gradients in primal-dual form, preconditioned by the
+ * cell-wise V-cycle of Algorithm 1 (zero initial guess, Sec. 5), coarse
+ * solve by a dense FP64 inverse.  b: dual FP64 (its boundary copies carry no
+ * equation and are ignored); x: primal FP64, initial guess on input (boundary
+ * copies set to zero), solution on output.  Setup (levels, diagonals, lambda_max
+ * estimates) happens on the first call with a given opts and is kept in the
+ * handle.  Synchronous; fills `report` if non-NULL.  Returns FE_ENOTCONV if
+ * maxit was reached. */
+fe_status pcg_solve(fe_problem* prob, const void* b_cell, void* x_cell, const fe_pcg_opts* opts,
+                    fe_pcg_report* report, void* stream);
+
+/* One application of the V-cycle preconditioner e = MG(b) (Algorithm 1 with
+ * a zero initial guess) on the finest level, in opts->inner precision.
+ * b: dual, e: primal, both in dtype `dt` == opts->inner. */
+fe_status fe_vcycle(fe_problem* prob, const void* b_cell, void* e_cell, const fe_pcg_opts* opts,
+                    fe_dtype dt, void* stream);
+
+/* lambda_max estimate of (patch inverse) * A on `level` by `steps` Lanczos
+ * steps (CG coefficients) from a fixed start vector.  Synchronous. */
+fe_status fe_estimate_lmax(fe_problem* prob, int level, int smoother, int factors, int steps,
+                           double* out, void* stream);
+
+/* Per-kernel timing with HIP events on the launch stream (tracing aid).
+ * enable = 1 starts recording, 0 stops; reset clears.  fe_prof_query
+ * synchronizes and returns, for kernel family `name`, the number of launches
+ * and the summed duration in milliseconds. */
+void fe_prof_enable(int enable);
+void fe_prof_reset(void);
+fe_status fe_prof_query(const char* name, int* count, double* total_ms);
+
+/* Thread-local description of the last non-OK status. */
+const char* fe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H */

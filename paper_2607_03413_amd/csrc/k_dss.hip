@@ -1,0 +1,241 @@
+// Gather G, assembly G^T, direct stiffness summation S and averaging S_bar,
+// and the assembled residual norm.
+//
+// Paper: G replicates, G^T sums the cell copies (Sec. 2.1); S = G G^T
+// (Sec. 4.1, eq. dss_operator); S_bar = G (G^T G)^{-1} G^T (Sec. 5,
+// eq. averaging_dss).  The paper evaluates S as d sequential axis passes over
+// interface pairs (Algorithm 7).  Here one thread owns one global node: it
+// reads every copy (at most 2^d, located by index arithmetic, no tables),
+// forms the sum in the cascade's order -- x pairs, then y pairs, then z
+// pairs -- and writes it to every copy.  Each copy belongs to exactly one
+// node, so the pass runs in place without atomics and without a second or
+// third launch, and the bits equal those of the cascade.  Interior nodes of a
+// cell (valence 1) are left untouched, which S and S_bar do anyway.
+#include "fe_internal.h"
+#include "kernel_common.h"
+
+namespace fe {
+
+template <int DIM>
+__device__ __forceinline__ void node_coords(int64_t g, int N, int& gx, int& gy, int& gz) {
+  gx = (int)(g % N);
+  const int64_t t = g / N;
+  if (DIM == 3) { gy = (int)(t % N); gz = (int)(t / N); }
+  else { gy = (int)t; gz = 0; }
+}
+
+template <typename T, int K, int DIM>
+__global__ void __launch_bounds__(256) k_dss(T* __restrict__ v, int n, int64_t n_nodes, int averaging) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_nodes) return;
+  const int N = (K - 1) * n + 1;
+  int gx, gy, gz;
+  node_coords<DIM>(g, N, gx, gy, gz);
+  const AxisCopies ax = axis_copies<K>(gx, n), ay = axis_copies<K>(gy, n);
+  const AxisCopies az = DIM == 3 ? axis_copies<K>(gz, n) : axis_copies<K>(1, n);
+  const int nz = DIM == 3 ? az.cnt : 1;
+  const int kappa = ax.cnt * ay.cnt * nz;
+  if (kappa == 1) return;
+  T s = cascade_sum<T, K, DIM>(v, ax, ay, az, n);
+  if (averaging) s *= T(1) / T(kappa);   // kappa is a power of two: exact
+  for (int sz = 0; sz < nz; ++sz)
+    for (int sy = 0; sy < ay.cnt; ++sy)
+      for (int sx = 0; sx < ax.cnt; ++sx) v[copy_addr<K, DIM>(ax, ay, az, sx, sy, sz, n)] = s;
+}
+
+template <typename T, int K, int DIM>
+__global__ void __launch_bounds__(256) k_assemble(const T* __restrict__ v, T* __restrict__ out, int n,
+                                                  int64_t n_nodes) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_nodes) return;
+  const int N = (K - 1) * n + 1;
+  int gx, gy, gz;
+  node_coords<DIM>(g, N, gx, gy, gz);
+  const AxisCopies ax = axis_copies<K>(gx, n), ay = axis_copies<K>(gy, n);
+  const AxisCopies az = DIM == 3 ? axis_copies<K>(gz, n) : axis_copies<K>(1, n);
+  out[g] = cascade_sum<T, K, DIM>(v, ax, ay, az, n);
+}
+
+template <typename T, int K, int DIM>
+__global__ void __launch_bounds__(256) k_gather(const T* __restrict__ xg, T* __restrict__ xc, int n,
+                                                int64_t len) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  constexpr int NL = DIM == 3 ? K * K * K : K * K;
+  constexpr int k = K - 1;
+  const int64_t cell = e / NL;
+  const int loc = (int)(e - cell * NL);
+  const int N = k * n + 1;
+  const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+  const int cx = (int)(cell % n);
+  const int64_t t = cell / n;
+  int64_t gidx;
+  if (DIM == 3) {
+    const int cy = (int)(t % n), cz = (int)(t / n);
+    gidx = (k * cx + ix) + (int64_t)N * ((k * cy + iy) + (int64_t)N * (k * cz + iz));
+  } else {
+    gidx = (k * cx + ix) + (int64_t)N * (k * (int)t + iy);
+  }
+  xc[e] = xg[gidx];
+}
+
+// Partial sums of (G^T r)_g^2 over the nodes, one value per block (FP64).
+template <typename T, int K, int DIM>
+__global__ void __launch_bounds__(256) k_assembled_norm2_partial(const T* __restrict__ v, int n,
+                                                                 int64_t n_nodes, double* __restrict__ part) {
+  const int N = (K - 1) * n + 1;
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_nodes;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int gx, gy, gz;
+    node_coords<DIM>(g, N, gx, gy, gz);
+    const AxisCopies ax = axis_copies<K>(gx, n), ay = axis_copies<K>(gy, n);
+    const AxisCopies az = DIM == 3 ? axis_copies<K>(gz, n) : axis_copies<K>(1, n);
+    const double s = (double)cascade_sum<T, K, DIM>(v, ax, ay, az, n);
+    acc += s * s;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out = S_bar r written to every copy (including valence-1 nodes), converted to
+// the output precision after the FP64 sum.  G^T out = G^T r, and the entries
+// are as small as the assembled residual, so a lower-precision copy keeps
+// G^T r accurate even when the raw copies of r are much larger than their sum.
+template <typename T, int K, int DIM>
+__global__ void __launch_bounds__(256) k_average_convert(const double* __restrict__ r, T* __restrict__ out, int n,
+                                                         int64_t n_nodes) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_nodes) return;
+  const int N = (K - 1) * n + 1;
+  int gx, gy, gz;
+  node_coords<DIM>(g, N, gx, gy, gz);
+  const AxisCopies ax = axis_copies<K>(gx, n), ay = axis_copies<K>(gy, n);
+  const AxisCopies az = DIM == 3 ? axis_copies<K>(gz, n) : axis_copies<K>(1, n);
+  const int nz = DIM == 3 ? az.cnt : 1;
+  const int kappa = ax.cnt * ay.cnt * nz;
+  const T s = (T)(cascade_sum<double, K, DIM>(r, ax, ay, az, n) * (1.0 / kappa));
+  for (int sz = 0; sz < nz; ++sz)
+    for (int sy = 0; sy < ay.cnt; ++sy)
+      for (int sx = 0; sx < ax.cnt; ++sx) out[copy_addr<K, DIM>(ax, ay, az, sx, sy, sz, n)] = s;
+}
+
+template <int K>
+static fe_status average_convert_typed(const fe_problem* p, int level, const double* r, void* out, fe_dtype dt,
+                                       hipStream_t s) {
+  const Level& L = level_of(p, level);
+  const int64_t N = (int64_t)p->k * L.n + 1;
+  const int64_t nn = p->dim == 3 ? N * N * N : N * N;
+  const unsigned nb = (unsigned)((nn + 255) / 256);
+  ProfScope ps("average_convert", s);
+  if (dt == FE_F32) {
+    if (p->dim == 3) hipLaunchKernelGGL((k_average_convert<float, K, 3>), dim3(nb), dim3(256), 0, s, r, (float*)out, L.n, nn);
+    else hipLaunchKernelGGL((k_average_convert<float, K, 2>), dim3(nb), dim3(256), 0, s, r, (float*)out, L.n, nn);
+  } else {
+    if (p->dim == 3) hipLaunchKernelGGL((k_average_convert<double, K, 3>), dim3(nb), dim3(256), 0, s, r, (double*)out, L.n, nn);
+    else hipLaunchKernelGGL((k_average_convert<double, K, 2>), dim3(nb), dim3(256), 0, s, r, (double*)out, L.n, nn);
+  }
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status launch_average_convert(const fe_problem* p, int level, const double* r, void* out, fe_dtype dt,
+                                 hipStream_t s) {
+  FE_DISPATCH_K(p->K, return average_convert_typed<KK>(p, level, r, out, dt, s));
+}
+
+fe_status finish_reduction(const fe_problem* p, int nparts, double* dev_out, hipStream_t s);
+
+static int64_t n_nodes_of(const fe_problem* p, const Level& L) {
+  const int64_t N = (int64_t)p->k * L.n + 1;
+  return p->dim == 3 ? N * N * N : N * N;
+}
+
+template <typename T, int K>
+static fe_status dss_typed(const fe_problem* p, const Level& L, T* v, int averaging, hipStream_t s) {
+  const int64_t nn = n_nodes_of(p, L);
+  const unsigned nb = (unsigned)((nn + 255) / 256);
+  ProfScope ps(averaging ? "dss_avg" : "dss_sum", s);
+  if (p->dim == 3)
+    hipLaunchKernelGGL((k_dss<T, K, 3>), dim3(nb), dim3(256), 0, s, v, L.n, nn, averaging);
+  else
+    hipLaunchKernelGGL((k_dss<T, K, 2>), dim3(nb), dim3(256), 0, s, v, L.n, nn, averaging);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+template <typename T, int K>
+static fe_status assemble_typed(const fe_problem* p, const Level& L, const T* v, T* out, hipStream_t s) {
+  const int64_t nn = n_nodes_of(p, L);
+  const unsigned nb = (unsigned)((nn + 255) / 256);
+  if (p->dim == 3)
+    hipLaunchKernelGGL((k_assemble<T, K, 3>), dim3(nb), dim3(256), 0, s, v, out, L.n, nn);
+  else
+    hipLaunchKernelGGL((k_assemble<T, K, 2>), dim3(nb), dim3(256), 0, s, v, out, L.n, nn);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+template <typename T, int K>
+static fe_status gather_typed(const fe_problem* p, const Level& L, const T* xg, T* xc, hipStream_t s) {
+  const unsigned nb = (unsigned)((L.len + 255) / 256);
+  if (p->dim == 3)
+    hipLaunchKernelGGL((k_gather<T, K, 3>), dim3(nb), dim3(256), 0, s, xg, xc, L.n, L.len);
+  else
+    hipLaunchKernelGGL((k_gather<T, K, 2>), dim3(nb), dim3(256), 0, s, xg, xc, L.n, L.len);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+template <typename T, int K>
+static fe_status norm2_typed(const fe_problem* p, const Level& L, const T* v, double* dev_out, hipStream_t s) {
+  const int64_t nn = n_nodes_of(p, L);
+  int nparts = (int)std::min<int64_t>(1024, (nn + 255) / 256);
+  double* part = p->red_scratch.as<double>();
+  ProfScope ps("assembled_norm2", s);
+  if (p->dim == 3)
+    hipLaunchKernelGGL((k_assembled_norm2_partial<T, K, 3>), dim3(nparts), dim3(256), 0, s, v, L.n, nn, part);
+  else
+    hipLaunchKernelGGL((k_assembled_norm2_partial<T, K, 2>), dim3(nparts), dim3(256), 0, s, v, L.n, nn, part);
+  FE_HIP_CHECK(hipGetLastError());
+  return finish_reduction(p, nparts, dev_out, s);
+}
+
+fe_status launch_dss(const fe_problem* p, int level, void* v, int averaging, fe_dtype dt, hipStream_t s) {
+  const Level& L = level_of(p, level);
+  if (dt == FE_F64) { FE_DISPATCH_K(p->K, return (dss_typed<double, KK>(p, L, (double*)v, averaging, s))); }
+  FE_DISPATCH_K(p->K, return (dss_typed<float, KK>(p, L, (float*)v, averaging, s)));
+}
+
+fe_status launch_assemble(const fe_problem* p, const void* yc, void* yg, fe_dtype dt, hipStream_t s) {
+  const Level& L = level_of(p, -1);
+  if (dt == FE_F64) {
+    FE_DISPATCH_K(p->K, return (assemble_typed<double, KK>(p, L, (const double*)yc, (double*)yg, s)));
+  }
+  FE_DISPATCH_K(p->K, return (assemble_typed<float, KK>(p, L, (const float*)yc, (float*)yg, s)));
+}
+
+fe_status launch_gather(const fe_problem* p, const void* xg, void* xc, fe_dtype dt, hipStream_t s) {
+  const Level& L = level_of(p, -1);
+  if (dt == FE_F64) {
+    FE_DISPATCH_K(p->K, return (gather_typed<double, KK>(p, L, (const double*)xg, (double*)xc, s)));
+  }
+  FE_DISPATCH_K(p->K, return (gather_typed<float, KK>(p, L, (const float*)xg, (float*)xc, s)));
+}
+
+fe_status assembled_norm2_async(const fe_problem* p, int level, const void* r, fe_dtype dt, double* dev_out,
+                                hipStream_t s) {
+  const Level& L = level_of(p, level);
+  if (dt == FE_F64) {
+    FE_DISPATCH_K(p->K, return (norm2_typed<double, KK>(p, L, (const double*)r, dev_out, s)));
+  }
+  FE_DISPATCH_K(p->K, return (norm2_typed<float, KK>(p, L, (const float*)r, dev_out, s)));
+}
+
+}  // namespace fe

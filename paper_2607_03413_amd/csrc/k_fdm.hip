@@ -1,0 +1,340 @@
+// Vertex-patch additive Schwarz inverse by fast diagonalization.
+//
+// The smoother is admissible in the sense of eq. precond_consistency
+// (P = G P_CG G^T, Sec. 2.1): it reads the residual only through its
+// assembly and returns a continuous correction.  For each interior vertex v
+// the patch unknowns are the m^d nodes (m = 2k-1) strictly inside the 2^d
+// cells around v.  With separable patch factors K_a S_a = M_a S_a L_a,
+// S_a^T M_a S_a = I (one pair per axis), A_p^{-1} = (S x S x S) (L + L + L)^{-1}
+// (S x S x S)^T.
+//
+// Two kernels:
+//  (1) one group of m^2 threads per patch: each thread sums the copies of one
+//      z-pencil of patch nodes (cascade order, straight from the cell-wise
+//      residual, so G^T r is never formed), applies S^T along z, y, x
+//      (pencils re-oriented through LDS), divides by the eigenvalue sums,
+//      applies S along x, y, z, and writes the m^d patch solution to a
+//      patch-major scratch buffer;
+//  (2) one thread per cell-wise entry sums the solutions of the (at most 2^d)
+//      patches containing its node, in a fixed order that depends only on the
+//      node, so every copy receives bit-identical values (continuity).
+#include "fe_internal.h"
+#include "kernel_common.h"
+
+namespace fe {
+
+template <int K>
+struct PatchDims {
+  static constexpr int k = K - 1;
+  static constexpr int M = 2 * k - 1;
+};
+
+// eig layout per patch (or shared): Sx, Sy, Sz (M*M each, row-major S[i*M+j]),
+// lx, ly, lz (M each).
+template <typename T, int M>
+struct EigPtrs {
+  const T *Sx, *Sy, *Sz, *lx, *ly, *lz;
+};
+
+template <typename T, int M, bool PER_PATCH>
+__device__ __forceinline__ EigPtrs<T, M> eig_ptrs(const T* __restrict__ eig, int64_t pid) {
+  EigPtrs<T, M> e;
+  if (PER_PATCH) {
+    const T* base = eig + pid * (3 * M * M + 3 * M);
+    e.Sx = base; e.Sy = base + M * M; e.Sz = base + 2 * M * M;
+    e.lx = base + 3 * M * M; e.ly = e.lx + M; e.lz = e.ly + M;
+  } else {
+    e.Sx = e.Sy = e.Sz = eig;
+    e.lx = e.ly = e.lz = eig + M * M;
+  }
+  return e;
+}
+
+template <typename T, int K, bool PER_PATCH>
+__global__ void __launch_bounds__(256) k_fdm_patch3(const T* __restrict__ r, T* __restrict__ W,
+                                                    const T* __restrict__ eig, T scale, int n,
+                                                    int64_t n_patches) {
+  constexpr int k = K - 1;
+  constexpr int M = 2 * k - 1;
+  constexpr int TPP = M * M;
+  constexpr int PPB = 256 / TPP > 0 ? 256 / TPP : 1;
+  constexpr int RS = M + 1;
+  constexpr int PS = M * RS;
+  constexpr int CS = M * PS;
+  __shared__ T sl[PPB * CS];
+  const int tid = threadIdx.x;
+  const int c = tid / TPP;
+  const int p = tid - c * TPP;
+  const int p0 = p % M, p1 = p / M;
+  const int64_t pid = (int64_t)blockIdx.x * PPB + c;
+  const bool active = pid < n_patches;
+  const int nv = n - 1;
+  int vx = 1, vy = 1, vz = 1;
+  if (active) {
+    vx = 1 + (int)(pid % nv);
+    const int64_t t = pid / nv;
+    vy = 1 + (int)(t % nv);
+    vz = 1 + (int)(t / nv);
+  }
+  const EigPtrs<T, M> E = eig_ptrs<T, M, PER_PATCH>(eig, active ? pid : 0);
+  T* ls = sl + c * CS;
+  T v[M], t[M];
+
+  // (a) gather the assembled residual on the z-pencil (a = p0, b = p1)
+  if (active) {
+    const AxisCopies ax = axis_copies<K>(k * (vx - 1) + p0 + 1, n);
+    const AxisCopies ay = axis_copies<K>(k * (vy - 1) + p1 + 1, n);
+#pragma unroll
+    for (int cz = 0; cz < M; ++cz) {
+      const AxisCopies az = axis_copies<K>(k * (vz - 1) + cz + 1, n);
+      v[cz] = cascade_sum<T, K, 3>(r, ax, ay, az, n);
+    }
+  } else {
+#pragma unroll
+    for (int cz = 0; cz < M; ++cz) v[cz] = T(0);
+  }
+  // (b) S_z^T along z
+  pencil_mtv<T, M>(E.Sz, v, t);
+#pragma unroll
+  for (int cz = 0; cz < M; ++cz) ls[cz * PS + p1 * RS + p0] = t[cz];
+  __syncthreads();
+  // (c) S_y^T along y: thread (a = p0, cz = p1)
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = ls[p1 * PS + j * RS + p0];
+  pencil_mtv<T, M>(E.Sy, v, t);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < M; ++b) ls[p1 * PS + b * RS + p0] = t[b];
+  __syncthreads();
+  // (d) x-pencil (b = p0, cz = p1): S_x^T, divide, S_x
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = ls[p1 * PS + p0 * RS + j];
+  pencil_mtv<T, M>(E.Sx, v, t);
+  {
+    const T lyz = E.ly[p0] + E.lz[p1];
+#pragma unroll
+    for (int a = 0; a < M; ++a) t[a] = t[a] * scale / (E.lx[a] + lyz);
+  }
+  pencil_mv<T, M>(E.Sx, t, v);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < M; ++a) ls[p1 * PS + p0 * RS + a] = v[a];
+  __syncthreads();
+  // (e) S_y along y: thread (a = p0, cz = p1)
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = ls[p1 * PS + j * RS + p0];
+  pencil_mv<T, M>(E.Sy, v, t);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < M; ++b) ls[p1 * PS + b * RS + p0] = t[b];
+  __syncthreads();
+  // (f) S_z along z: thread (a = p0, b = p1); write the patch solution
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = ls[j * PS + p1 * RS + p0];
+  pencil_mv<T, M>(E.Sz, v, t);
+  if (active) {
+    T* w = W + pid * (M * M * M) + p1 * M + p0;
+#pragma unroll
+    for (int cz = 0; cz < M; ++cz) w[cz * M * M] = t[cz];
+  }
+}
+
+template <typename T, int K, bool PER_PATCH>
+__global__ void __launch_bounds__(256) k_fdm_patch2(const T* __restrict__ r, T* __restrict__ W,
+                                                    const T* __restrict__ eig, T scale, int n,
+                                                    int64_t n_patches) {
+  constexpr int k = K - 1;
+  constexpr int M = 2 * k - 1;
+  constexpr int TPP = M;
+  constexpr int PPB = 256 / TPP;
+  constexpr int RS = M + 1;
+  constexpr int CS = M * RS;
+  __shared__ T sl[PPB * CS];
+  const int tid = threadIdx.x;
+  const int c = tid / TPP;
+  const int p = tid - c * TPP;
+  const int64_t pid = (int64_t)blockIdx.x * PPB + c;
+  const bool active = pid < n_patches;
+  const int nv = n - 1;
+  int vx = 1, vy = 1;
+  if (active) { vx = 1 + (int)(pid % nv); vy = 1 + (int)(pid / nv); }
+  const EigPtrs<T, M> E = eig_ptrs<T, M, PER_PATCH>(eig, active ? pid : 0);
+  T* ls = sl + c * CS;
+  T v[M], t[M];
+  // y-pencil at a = p
+  if (active) {
+    const AxisCopies ax = axis_copies<K>(k * (vx - 1) + p + 1, n);
+    const AxisCopies az = ax;
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      const AxisCopies ay = axis_copies<K>(k * (vy - 1) + b + 1, n);
+      v[b] = cascade_sum<T, K, 2>(r, ax, ay, az, n);
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < M; ++b) v[b] = T(0);
+  }
+  pencil_mtv<T, M>(E.Sy, v, t);
+#pragma unroll
+  for (int b = 0; b < M; ++b) ls[b * RS + p] = t[b];
+  __syncthreads();
+  // x-pencil at b = p
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = ls[p * RS + j];
+  pencil_mtv<T, M>(E.Sx, v, t);
+  {
+    const T ly = E.ly[p];
+#pragma unroll
+    for (int a = 0; a < M; ++a) t[a] = t[a] * scale / (E.lx[a] + ly);
+  }
+  pencil_mv<T, M>(E.Sx, t, v);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < M; ++a) ls[p * RS + a] = v[a];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = ls[j * RS + p];
+  pencil_mv<T, M>(E.Sy, v, t);
+  if (active) {
+    T* w = W + pid * (M * M) + p;
+#pragma unroll
+    for (int b = 0; b < M; ++b) w[b * M] = t[b];
+  }
+}
+
+// Patches containing node coordinate g along one axis: vertex v with
+// k(v-1) < g < k(v+1) and 1 <= v <= n-1; offset o = g - k(v-1) - 1.
+struct AxisPatches {
+  int cnt;
+  int v[2];
+  int o[2];
+};
+
+template <int K>
+__device__ __forceinline__ AxisPatches axis_patches(int g, int n) {
+  constexpr int k = K - 1;
+  AxisPatches a;
+  a.cnt = 0;
+  const int q = g / k, r = g - q * k;
+  if (r == 0) {
+    if (q >= 1 && q <= n - 1) { a.v[0] = q; a.o[0] = k - 1; a.cnt = 1; }
+  } else {
+    if (q >= 1) { a.v[a.cnt] = q; a.o[a.cnt] = k + r - 1; ++a.cnt; }
+    if (q + 1 <= n - 1) { a.v[a.cnt] = q + 1; a.o[a.cnt] = r - 1; ++a.cnt; }
+  }
+  return a;
+}
+
+template <typename T, int K, int DIM>
+__global__ void __launch_bounds__(256) k_fdm_sum(const T* __restrict__ W, T* __restrict__ z, int n,
+                                                 int64_t len) {
+  constexpr int k = K - 1;
+  constexpr int M = 2 * k - 1;
+  constexpr int NL = DIM == 3 ? K * K * K : K * K;
+  constexpr int MP = DIM == 3 ? M * M * M : M * M;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const int64_t cell = e / NL;
+  const int loc = (int)(e - cell * NL);
+  const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+  const int cx = (int)(cell % n);
+  const int64_t t = cell / n;
+  const int nv = n - 1;
+  T s = T(0);
+  if (DIM == 3) {
+    const int cy = (int)(t % n), cz = (int)(t / n);
+    const AxisPatches px = axis_patches<K>(k * cx + ix, n);
+    const AxisPatches py = axis_patches<K>(k * cy + iy, n);
+    const AxisPatches pz = axis_patches<K>(k * cz + iz, n);
+    for (int a = 0; a < pz.cnt; ++a)
+      for (int b = 0; b < py.cnt; ++b)
+        for (int c = 0; c < px.cnt; ++c) {
+          const int64_t pid = (px.v[c] - 1) + (int64_t)nv * ((py.v[b] - 1) + (int64_t)nv * (pz.v[a] - 1));
+          s += W[pid * MP + px.o[c] + M * (py.o[b] + M * pz.o[a])];
+        }
+  } else {
+    const int cy = (int)t;
+    const AxisPatches px = axis_patches<K>(k * cx + ix, n);
+    const AxisPatches py = axis_patches<K>(k * cy + iy, n);
+    for (int b = 0; b < py.cnt; ++b)
+      for (int c = 0; c < px.cnt; ++c) {
+        const int64_t pid = (px.v[c] - 1) + (int64_t)nv * (py.v[b] - 1);
+        s += W[pid * MP + px.o[c] + M * py.o[b]];
+      }
+  }
+  z[e] = s;
+}
+
+size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt) {
+  const Level& L = level_of(p, level);
+  const int64_t nv = L.n - 1;
+  const int64_t M = 2 * p->k - 1;
+  const int64_t np = p->dim == 3 ? nv * nv * nv : nv * nv;
+  const int64_t mp = p->dim == 3 ? M * M * M : M * M;
+  return (size_t)(np * mp) * (dt == FE_F64 ? 8 : 4);
+}
+
+template <typename T, int K>
+static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T* z, T* W, const T* eig,
+                             bool per_patch, T scale, hipStream_t s) {
+  constexpr int M = 2 * (K - 1) - 1;
+  const int64_t nv = L.n - 1;
+  if (p->dim == 3) {
+    const int64_t np = nv * nv * nv;
+    if (np > 0) {
+      constexpr int PPB = 256 / (M * M) > 0 ? 256 / (M * M) : 1;
+      const unsigned nb = (unsigned)((np + PPB - 1) / PPB);
+      ProfScope ps("fdm_patch", s);
+      if (per_patch)
+        hipLaunchKernelGGL((k_fdm_patch3<T, K, true>), dim3(nb), dim3(PPB * M * M), 0, s, r, W, eig, scale, L.n, np);
+      else
+        hipLaunchKernelGGL((k_fdm_patch3<T, K, false>), dim3(nb), dim3(PPB * M * M), 0, s, r, W, eig, scale, L.n, np);
+      FE_HIP_CHECK(hipGetLastError());
+    }
+    ProfScope ps2("fdm_sum", s);
+    hipLaunchKernelGGL((k_fdm_sum<T, K, 3>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
+                       L.len);
+  } else {
+    const int64_t np = nv * nv;
+    if (np > 0) {
+      constexpr int PPB = 256 / M;
+      const unsigned nb = (unsigned)((np + PPB - 1) / PPB);
+      ProfScope ps("fdm_patch", s);
+      if (per_patch)
+        hipLaunchKernelGGL((k_fdm_patch2<T, K, true>), dim3(nb), dim3(PPB * M), 0, s, r, W, eig, scale, L.n, np);
+      else
+        hipLaunchKernelGGL((k_fdm_patch2<T, K, false>), dim3(nb), dim3(PPB * M), 0, s, r, W, eig, scale, L.n, np);
+      FE_HIP_CHECK(hipGetLastError());
+    }
+    ProfScope ps2("fdm_sum", s);
+    hipLaunchKernelGGL((k_fdm_sum<T, K, 2>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
+                       L.len);
+  }
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status launch_patch_inverse(const fe_problem* p, int level, const void* r, void* z, void* scratch,
+                               fe_dtype dt, int factors, hipStream_t s) {
+  const Level& L = level_of(p, level);
+  const bool per_patch = factors != 0;
+  const double scale = per_patch ? 1.0 : std::pow(L.h, 2 - p->dim);
+  const int li = level < 0 ? (int)p->levels.size() - 1 : level;
+  const void* eig;
+  if (per_patch) {
+    const Level& LL = p->levels[li];
+    if (!LL.patch_eig_ready[factors]) return fail(FE_EINVAL, "patch factors not available for this mode");
+    eig = dt == FE_F64 ? LL.patch_eig64[factors].p : LL.patch_eig32[factors].p;
+  } else {
+    eig = dt == FE_F64 ? (const void*)(p->coef64.as<double>() + p->co.off_S)
+                       : (const void*)(p->coef32.as<float>() + p->co.off_S);
+  }
+  if (dt == FE_F64) {
+    FE_DISPATCH_K(p->K, return (patch_typed<double, KK>(p, L, (const double*)r, (double*)z, (double*)scratch,
+                                                        (const double*)eig, per_patch, scale, s)));
+  }
+  FE_DISPATCH_K(p->K, return (patch_typed<float, KK>(p, L, (const float*)r, (float*)z, (float*)scratch,
+                                                     (const float*)eig, per_patch, (float)scale, s)));
+}
+
+}  // namespace fe

@@ -1,0 +1,416 @@
+// Cell-wise geometric multigrid V-cycle and primal-dual preconditioned CG.
+//
+// V-cycle: Algorithm 1 with a zero initial guess (Sec. 5: the preconditioner
+// skips the first operator application), residual restriction fused with
+// the residual formation (Sec. 5), coarse solve by a dense FP64 inverse.
+// Smoothers:
+//   Jacobi:  the fused sweep of Algorithm 9 (apply, raw per-copy update with
+//            the valence-baked masked inverse diagonal, averaging DSS);
+//   Cheb-FDM: Chebyshev semi-iteration of degree d preconditioned by the
+//            vertex-patch inverse, an admissible smoother of the form
+//            G P_CG G^T (eq. precond_consistency).
+// PCG: Sec. 4.4, all inner products pair a dual with a primal vector and are
+// therefore local (eq. pairing_global); the stopping test uses the assembled
+// residual ||G^T r||_2.  The V-cycle may run in FP32 inside the FP64
+// iteration; the flexible (Polak-Ribiere) beta then keeps the iteration
+// robust to the small nonlinearity of the rounded preconditioner.
+#include <chrono>
+#include <cmath>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+fe_status ensure_dinv_level(fe_problem* p, int li, hipStream_t s);
+fe_status ensure_coarse_inverse(fe_problem* p, hipStream_t s);
+
+struct Solver {
+  fe_pcg_opts opts{};
+  bool ready = false;
+  int inner = FE_F64;
+  DeviceBuf r, z, pv, q, zf;  // finest-level FP64 PCG vectors
+  DeviceBuf dscal;             // device doubles for reductions
+};
+
+static bool same_setup(const fe_pcg_opts& a, const fe_pcg_opts& b) {
+  return a.smoother == b.smoother && a.cheb_degree == b.cheb_degree && a.cheb_ratio == b.cheb_ratio &&
+         a.cheb_lmax == b.cheb_lmax && a.inner == b.inner && a.factors == b.factors && a.precond == b.precond;
+}
+
+static double* dev_scalar(fe_problem* p, int i) { return p->solver->dscal.as<double>() + i; }
+
+static fe_status read_scalar(fe_problem* p, int i, double* out, hipStream_t s) {
+  FE_HIP_CHECK(hipMemcpyAsync(out, dev_scalar(p, i), sizeof(double), hipMemcpyDeviceToHost, s));
+  FE_HIP_CHECK(hipStreamSynchronize(s));
+  return FE_OK;
+}
+
+static fe_status patch_apply(fe_problem* p, int l, const void* r, void* z, fe_dtype dt, int factors, hipStream_t s) {
+  Level& L = p->levels[l];
+  DeviceBuf& scr = L.fdm_scratch[dt == FE_F64 ? 0 : 1];
+  FE_CHECK(scr.alloc(patch_scratch_bytes(p, l, dt)));
+  return launch_patch_inverse(p, l, r, z, scr.p, dt, factors, s);
+}
+
+// lambda_max of (patch inverse) A on level l by CG-Lanczos from a fixed start vector.
+static fe_status estimate_lmax(fe_problem* p, int l, int factors, int steps, double* out, hipStream_t s) {
+  Level& L = p->levels[l];
+  const int64_t n = L.len;
+  DeviceBuf x, r, z, pp, q;
+  for (DeviceBuf* b : {&x, &r, &z, &pp, &q}) FE_CHECK(b->alloc(n * sizeof(double)));
+  // start vector: deterministic hash of the index (counter based), dual
+  std::vector<double> h(n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t zq = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    zq = (zq ^ (zq >> 30)) * 0xBF58476D1CE4E5B9ull;
+    zq = (zq ^ (zq >> 27)) * 0x94D049BB133111EBull;
+    zq ^= zq >> 31;
+    h[i] = (double)(zq >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+  FE_HIP_CHECK(hipMemcpyAsync(r.p, h.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  std::vector<double> alpha, beta;
+  FE_CHECK(patch_apply(p, l, r.p, z.p, FE_F64, factors, s));
+  FE_CHECK(launch_cast(n, z.p, FE_F64, pp.p, FE_F64, s));
+  FE_CHECK(dot_async(p, n, r.p, z.p, FE_F64, dev_scalar(p, 0), s));
+  double rho;
+  FE_CHECK(read_scalar(p, 0, &rho, s));
+  for (int it = 0; it < steps; ++it) {
+    FE_CHECK(launch_apply(p, l, pp.p, q.p, FE_F64, s));
+    FE_CHECK(dot_async(p, n, pp.p, q.p, FE_F64, dev_scalar(p, 0), s));
+    double pq;
+    FE_CHECK(read_scalar(p, 0, &pq, s));
+    if (!(pq > 0.0) || !(rho > 0.0)) break;
+    const double a = rho / pq;
+    alpha.push_back(a);
+    FE_CHECK(launch_axpby(n, -a, q.p, 1.0, r.p, FE_F64, s));
+    FE_CHECK(patch_apply(p, l, r.p, z.p, FE_F64, factors, s));
+    FE_CHECK(dot_async(p, n, r.p, z.p, FE_F64, dev_scalar(p, 0), s));
+    double rho2;
+    FE_CHECK(read_scalar(p, 0, &rho2, s));
+    const double b = rho2 / rho;
+    beta.push_back(b);
+    rho = rho2;
+    FE_CHECK(launch_axpby(n, 1.0, z.p, b, pp.p, FE_F64, s));
+  }
+  const int m = (int)alpha.size();
+  if (m == 0) return fail(FE_EBREAKDOWN, "Lanczos estimate broke down");
+  // Lanczos tridiagonal from the CG coefficients
+  std::vector<double> T(m * m, 0.0), I(m * m, 0.0), S, lam;
+  for (int i = 0; i < m; ++i) {
+    I[i * m + i] = 1.0;
+    T[i * m + i] = 1.0 / alpha[i] + (i > 0 ? beta[i - 1] / alpha[i - 1] : 0.0);
+    if (i + 1 < m) T[i * m + i + 1] = T[(i + 1) * m + i] = std::sqrt(beta[i]) / alpha[i];
+  }
+  if (!sym_generalized_eig(m, T, I, S, lam)) return fail(FE_EBREAKDOWN, "tridiagonal eigensolve failed");
+  *out = lam[m - 1];
+  return FE_OK;
+}
+
+fe_status solver_setup(fe_problem* p, const fe_pcg_opts* o, hipStream_t s) {
+  if (p->dim != 3) return fail(FE_EUNSUPPORTED, "the multigrid solver is implemented for d = 3");
+  if (p->bc != 1) return fail(FE_EINVAL, "the solver needs homogeneous Dirichlet conditions (bc = 1)");
+  FE_CHECK(ensure_coarse_inverse(p, s));
+  if (!p->solver) p->solver = new Solver();
+  Solver& S = *p->solver;
+  if (S.ready && same_setup(S.opts, *o)) {
+    S.opts = *o;
+    return FE_OK;
+  }
+  const int nl = (int)p->levels.size();
+  const int64_t nfine = p->levels.back().len;
+  FE_CHECK(S.dscal.alloc(64 * sizeof(double)));
+  for (DeviceBuf* b : {&S.r, &S.z, &S.pv, &S.q}) FE_CHECK(b->alloc(nfine * sizeof(double)));
+  const int di = o->inner == FE_F64 ? 0 : 1;
+  const size_t es = o->inner == FE_F64 ? 8 : 4;
+  for (int l = 0; l < nl; ++l) {
+    Level& L = p->levels[l];
+    for (DeviceBuf* b : {&L.e[di], &L.b[di], &L.v[di], &L.t[di], &L.w[di]}) FE_CHECK(b->alloc(L.len * es));
+    if (l > 0 && o->smoother == FE_SMOOTH_JACOBI) FE_CHECK(ensure_dinv_level(p, l, s));
+    if (l > 0 && o->smoother == FE_SMOOTH_CHEB_FDM) {
+      if (o->factors != 0 && !L.patch_eig_ready[o->factors]) FE_CHECK(setup_patch_factors(p, l, o->factors, s));
+      const int key = o->factors * 1000 + 15;
+      if (o->cheb_lmax > 0.0) {
+        L.lmax = o->cheb_lmax;
+      } else if (L.lmax_key != key) {
+        double lm;
+        FE_CHECK(estimate_lmax(p, l, o->factors, 15, &lm, s));
+        L.lmax = lm;
+        L.lmax_key = key;
+      }
+    }
+  }
+  FE_HIP_CHECK(hipStreamSynchronize(s));
+  S.opts = *o;
+  S.ready = true;
+  return FE_OK;
+}
+
+void solver_destroy(fe_problem* p) {
+  delete p->solver;
+  p->solver = nullptr;
+}
+
+// ---------------------------------------------------------------- smoothers
+static fe_status jacobi_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe_dtype dt, hipStream_t s) {
+  Level& L = p->levels[l];
+  const int di = dt == FE_F64 ? 0 : 1;
+  const void* dinv = dt == FE_F64 ? L.dinv64.p : L.dinv32.p;
+  const double omega = p->solver->opts.omega;
+  for (int it = 0; it < sweeps; ++it) {
+    const bool z = u_zero && it == 0;
+    if (!z) FE_CHECK(launch_apply(p, l, L.e[di].p, L.v[di].p, dt, s));
+    FE_CHECK(launch_jacobi_update(p, l, L.b[di].p, L.v[di].p, L.e[di].p, dinv, omega, z ? 1 : 0, dt, s));
+    FE_CHECK(launch_dss(p, l, L.e[di].p, 1, dt, s));
+  }
+  return FE_OK;
+}
+
+// Chebyshev semi-iteration on [lmax/ratio, lmax] preconditioned by the patch inverse.
+// Buffers: e = iterate, b = rhs, t = residual (dual), w = direction (primal),
+// v = A w (dual), and the patch output reuses v's role through y = w's update.
+static fe_status cheb_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe_dtype dt, hipStream_t s) {
+  Level& L = p->levels[l];
+  const int di = dt == FE_F64 ? 0 : 1;
+  const fe_pcg_opts& o = p->solver->opts;
+  const double lmax = 1.2 * L.lmax, lmin = lmax / o.cheb_ratio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  const int64_t n = L.len;
+  void *e = L.e[di].p, *b = L.b[di].p, *t = L.t[di].p, *w = L.w[di].p, *v = L.v[di].p;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    const bool z = u_zero && sw == 0;
+    double rho = 1.0 / sigma;
+    // t = b - A e
+    if (z) {
+      FE_CHECK(launch_cast(n, b, dt, t, dt, s));
+    } else {
+      FE_CHECK(launch_apply(p, l, e, v, dt, s));
+      FE_CHECK(launch_cast(n, b, dt, t, dt, s));
+      FE_CHECK(launch_axpby(n, -1.0, v, 1.0, t, dt, s));
+    }
+    // w = P t / theta; e += w
+    FE_CHECK(patch_apply(p, l, t, w, dt, o.factors, s));
+    FE_CHECK(launch_axpby(n, 1.0 / theta, w, 0.0, w, dt, s));
+    if (z) FE_CHECK(launch_cast(n, w, dt, e, dt, s));
+    else FE_CHECK(launch_axpby(n, 1.0, w, 1.0, e, dt, s));
+    for (int it = 1; it < o.cheb_degree; ++it) {
+      FE_CHECK(launch_apply(p, l, w, v, dt, s));          // v = A w
+      FE_CHECK(launch_axpby(n, -1.0, v, 1.0, t, dt, s));  // t -= A w
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      FE_CHECK(patch_apply(p, l, t, v, dt, o.factors, s));  // v = P t (primal)
+      FE_CHECK(launch_axpby(n, 2.0 * rho_new / delta, v, rho_new * rho, w, dt, s));
+      FE_CHECK(launch_axpby(n, 1.0, w, 1.0, e, dt, s));
+      rho = rho_new;
+    }
+  }
+  return FE_OK;
+}
+
+static fe_status smooth(fe_problem* p, int l, bool pre, bool u_zero, fe_dtype dt, hipStream_t s) {
+  const fe_pcg_opts& o = p->solver->opts;
+  const int sweeps = pre ? o.nu_pre : o.nu_post;
+  if (sweeps <= 0) {
+    if (u_zero) FE_CHECK(launch_fill(p->levels[l].len, p->levels[l].e[dt == FE_F64 ? 0 : 1].p, 0.0, dt, s));
+    return FE_OK;
+  }
+  if (o.smoother == FE_SMOOTH_JACOBI) return jacobi_smooth(p, l, sweeps, u_zero, dt, s);
+  return cheb_smooth(p, l, sweeps, u_zero, dt, s);
+}
+
+// e_l = MG(b_l) with zero initial guess; b_l, e_l live in the level buffers.
+static fe_status vcycle_level(fe_problem* p, int l, fe_dtype dt, hipStream_t s) {
+  Level& L = p->levels[l];
+  const int di = dt == FE_F64 ? 0 : 1;
+  if (l == 0) return launch_coarse_solve(p, L.b[di].p, L.e[di].p, dt, s);
+  FE_CHECK(smooth(p, l, true, true, dt, s));
+  FE_CHECK(launch_apply(p, l, L.e[di].p, L.v[di].p, dt, s));
+  Level& C = p->levels[l - 1];
+  FE_CHECK(launch_restrict(p, l, L.b[di].p, L.v[di].p, C.b[di].p, dt, s));
+  FE_CHECK(vcycle_level(p, l - 1, dt, s));
+  FE_CHECK(launch_prolongate_add(p, l, C.e[di].p, L.e[di].p, dt, s));
+  return smooth(p, l, false, false, dt, s);
+}
+
+fe_status solver_vcycle(fe_problem* p, const fe_pcg_opts* o, fe_dtype dt, hipStream_t s) {
+  (void)o;
+  return vcycle_level(p, (int)p->levels.size() - 1, dt, s);
+}
+
+// z = M r (finest level): r, z FP64
+static fe_status precondition(fe_problem* p, const void* r, void* z, hipStream_t s) {
+  Solver& S = *p->solver;
+  Level& F = p->levels.back();
+  const fe_dtype dt = (fe_dtype)S.opts.inner;
+  const int di = dt == FE_F64 ? 0 : 1;
+  if (!S.opts.precond) return launch_cast(F.len, r, FE_F64, z, FE_F64, s);
+  // The preconditioner reads r only through G^T r, so an FP32 V-cycle is fed
+  // the averaged copies S_bar r (formed in FP64): the raw copies of a residual
+  // near convergence are far larger than their sum, and rounding them to FP32
+  // first would bury G^T r.
+  if (dt == FE_F32) FE_CHECK(launch_average_convert(p, -1, (const double*)r, F.b[di].p, dt, s));
+  else FE_CHECK(launch_cast(F.len, r, FE_F64, F.b[di].p, dt, s));
+  FE_CHECK(vcycle_level(p, (int)p->levels.size() - 1, dt, s));
+  return launch_cast(F.len, F.e[di].p, dt, z, FE_F64, s);
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+void fe_pcg_default_opts(fe_pcg_opts* o) {
+  if (!o) return;
+  o->tol = 1e-10;
+  o->maxit = 200;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->smoother = FE_SMOOTH_JACOBI;
+  o->cheb_degree = 3;
+  o->cheb_ratio = 20.0;
+  o->cheb_lmax = 0.0;
+  o->omega = 0.7;
+  o->inner = FE_F64;
+  o->factors = 0;
+  o->flexible = 0;
+  o->precond = 1;
+}
+
+static fe_status check_opts(const fe_problem* p, const fe_pcg_opts* o) {
+  if (!o) return fail(FE_EINVAL, "null opts");
+  if (o->inner != FE_F64 && o->inner != FE_F32) return fail(FE_EINVAL, "bad inner precision");
+  if (o->smoother != FE_SMOOTH_JACOBI && o->smoother != FE_SMOOTH_CHEB_FDM) return fail(FE_EINVAL, "bad smoother");
+  if (o->smoother == FE_SMOOTH_CHEB_FDM && (o->cheb_degree < 1 || o->cheb_ratio <= 1.0))
+    return fail(FE_EINVAL, "bad Chebyshev parameters");
+  if (o->smoother == FE_SMOOTH_CHEB_FDM && o->factors == 0 && p->desc.geometry != FE_GEOM_CARTESIAN)
+    return fail(FE_EINVAL, "exact separable factors need the Cartesian mesh");
+  if (o->smoother == FE_SMOOTH_CHEB_FDM && o->factors != 0 && p->desc.geometry != FE_GEOM_DEFORMED)
+    return fail(FE_EINVAL, "per-patch factors need the deformed geometry");
+  if (o->factors < 0 || o->factors > 2) return fail(FE_EINVAL, "bad factors");
+  if (o->nu_pre < 0 || o->nu_post < 0 || o->maxit < 0) return fail(FE_EINVAL, "negative counts");
+  if (!(o->tol >= 0.0)) return fail(FE_EINVAL, "bad tolerance");
+  return FE_OK;
+}
+
+fe_status fe_vcycle(fe_problem* p, const void* b, void* e, const fe_pcg_opts* o, fe_dtype dt, void* stream) {
+  if (!p) return fail(FE_EINVAL, "null problem");
+  FE_CHECK(check_opts(p, o));
+  if (dt != (fe_dtype)o->inner) return fail(FE_EINVAL, "dtype must equal opts->inner");
+  FE_CHECK(check_ptr(b, "b"));
+  FE_CHECK(check_ptr(e, "e"));
+  hipStream_t s = (hipStream_t)stream;
+  FE_CHECK(solver_setup(p, o, s));
+  Level& F = p->levels.back();
+  const int di = dt == FE_F64 ? 0 : 1;
+  FE_CHECK(launch_cast(F.len, b, dt, F.b[di].p, dt, s));
+  FE_CHECK(vcycle_level(p, (int)p->levels.size() - 1, dt, s));
+  return launch_cast(F.len, F.e[di].p, dt, e, dt, s);
+}
+
+fe_status fe_estimate_lmax(fe_problem* p, int level, int smoother, int factors, int steps, double* out,
+                           void* stream) {
+  if (!p || !out) return fail(FE_EINVAL, "null argument");
+  FE_CHECK(check_level(p, level));
+  if (smoother != FE_SMOOTH_CHEB_FDM) return fail(FE_EINVAL, "only the patch-preconditioned operator is supported");
+  if (steps < 1 || steps > 200) return fail(FE_EINVAL, "steps out of range");
+  hipStream_t s = (hipStream_t)stream;
+  const int l = level < 0 ? (int)p->levels.size() - 1 : level;
+  if (factors != 0 && !p->levels[l].patch_eig_ready[factors]) FE_CHECK(setup_patch_factors(p, l, factors, s));
+  if (!p->solver) p->solver = new Solver();
+  FE_CHECK(p->solver->dscal.alloc(64 * sizeof(double)));
+  return estimate_lmax(p, l, factors, steps, out, s);
+}
+
+fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o, fe_pcg_report* rep, void* stream) {
+  using clk = std::chrono::steady_clock;
+  if (!p) return fail(FE_EINVAL, "null problem");
+  FE_CHECK(check_opts(p, o));
+  FE_CHECK(check_ptr(b, "b_cell"));
+  FE_CHECK(check_ptr(x, "x_cell"));
+  hipStream_t s = (hipStream_t)stream;
+  auto t0 = clk::now();
+  FE_CHECK(solver_setup(p, o, s));
+  FE_HIP_CHECK(hipStreamSynchronize(s));
+  auto t1 = clk::now();
+  Solver& S = *p->solver;
+  Level& F = p->levels.back();
+  const int64_t n = F.len;
+  void *r = S.r.p, *z = S.z.p, *pv = S.pv.p, *q = S.q.p;
+  double nb2, rr2;
+  // Dirichlet problem: the residual lives in the dual of the interior space, so
+  // the boundary copies of b are masked out (they carry no equation).
+  FE_CHECK(launch_cast(n, b, FE_F64, r, FE_F64, s));
+  FE_CHECK(launch_mask_boundary(p, -1, r, FE_F64, s));
+  FE_CHECK(assembled_norm2_async(p, -1, r, FE_F64, dev_scalar(p, 1), s));
+  FE_CHECK(read_scalar(p, 1, &nb2, s));
+  // r = M (b - A x)
+  FE_CHECK(launch_mask_boundary(p, -1, x, FE_F64, s));
+  FE_CHECK(launch_apply(p, -1, x, q, FE_F64, s));
+  FE_CHECK(launch_axpby(n, -1.0, q, 1.0, r, FE_F64, s));
+  FE_CHECK(assembled_norm2_async(p, -1, r, FE_F64, dev_scalar(p, 1), s));
+  FE_CHECK(read_scalar(p, 1, &rr2, s));
+  const double nb = std::sqrt(nb2);
+  double relres = nb > 0 ? std::sqrt(rr2) / nb : 0.0;
+  fe_pcg_report R{};
+  fe_status result = FE_OK;
+  int it = 0;
+  if (!std::isfinite(relres)) result = fail(FE_EBREAKDOWN, "non-finite right-hand side or initial residual");
+  if (result == FE_OK && relres > o->tol) {
+    FE_CHECK(precondition(p, r, z, s));
+    FE_CHECK(launch_cast(n, z, FE_F64, pv, FE_F64, s));
+    double rho;
+    FE_CHECK(dot_async(p, n, r, z, FE_F64, dev_scalar(p, 0), s));
+    FE_CHECK(read_scalar(p, 0, &rho, s));
+    R.energy0 = rho;
+    R.energy = rho;
+    if (!(rho > 0.0)) result = fail(FE_EBREAKDOWN, "<r, z> <= 0 at start: preconditioner not positive");
+    while (result == FE_OK && it < o->maxit) {
+      ++it;
+      FE_CHECK(launch_apply(p, -1, pv, q, FE_F64, s));
+      double pq;
+      FE_CHECK(dot_async(p, n, pv, q, FE_F64, dev_scalar(p, 0), s));
+      FE_CHECK(read_scalar(p, 0, &pq, s));
+      if (!(pq > 0.0) || !std::isfinite(pq)) {
+        result = fail(FE_EBREAKDOWN, "<p, A p> <= 0");
+        break;
+      }
+      const double alpha = rho / pq;
+      FE_CHECK(launch_axpby(n, alpha, pv, 1.0, x, FE_F64, s));
+      FE_CHECK(launch_axpby(n, -alpha, q, 1.0, r, FE_F64, s));
+      FE_CHECK(assembled_norm2_async(p, -1, r, FE_F64, dev_scalar(p, 1), s));
+      double rz_old = 0.0;
+      if (o->flexible) FE_CHECK(dot_async(p, n, r, z, FE_F64, dev_scalar(p, 2), s));
+      FE_CHECK(read_scalar(p, 1, &rr2, s));
+      relres = std::sqrt(rr2) / nb;
+      if (!std::isfinite(relres)) {
+        result = fail(FE_EBREAKDOWN, "non-finite residual");
+        break;
+      }
+      if (relres <= o->tol) break;
+      if (o->flexible) FE_CHECK(read_scalar(p, 2, &rz_old, s));
+      FE_CHECK(precondition(p, r, z, s));
+      double rho_new;
+      FE_CHECK(dot_async(p, n, r, z, FE_F64, dev_scalar(p, 0), s));
+      FE_CHECK(read_scalar(p, 0, &rho_new, s));
+      R.energy = rho_new;
+      if (!(rho_new > 0.0)) {
+        result = fail(FE_EBREAKDOWN, "<r, z> <= 0: preconditioner not positive");
+        break;
+      }
+      const double beta = o->flexible ? (rho_new - rz_old) / rho : rho_new / rho;
+      FE_CHECK(launch_axpby(n, 1.0, z, beta, pv, FE_F64, s));
+      rho = rho_new;
+    }
+    if (result == FE_OK && relres > o->tol) result = fail(FE_ENOTCONV, "maximum number of iterations reached");
+  }
+  FE_HIP_CHECK(hipStreamSynchronize(s));
+  auto t2 = clk::now();
+  R.iters = it;
+  R.relres = relres;
+  R.converged = relres <= o->tol ? 1 : 0;
+  R.t_setup = std::chrono::duration<double>(t1 - t0).count();
+  R.t_solve = std::chrono::duration<double>(t2 - t1).count();
+  if (rep) *rep = R;
+  return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+"""Thin ctypes binding of libfe.so (include/fe.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are torch tensors (``torch`` is used for device
+memory and streams); calls run on torch's current stream.  The library must
+be built (``paper_2607_03413_amd/build_lib.py``); importing this module
+without it raises immediately -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfe.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libfe.so is not built: run paper_2607_03413_amd/build_lib.py")
+_lib = ctypes.CDLL(LIB_PATH)
+
+F64, F32 = 0, 1
+GEOM_CARTESIAN, GEOM_DEFORMED = 0, 1
+SMOOTH_JACOBI, SMOOTH_CHEB_FDM = 0, 1
+STATUS = {0: "FE_OK", -1: "FE_EINVAL", -2: "FE_ENOMEM", -3: "FE_EHIP", -4: "FE_ENOTCONV",
+          -5: "FE_EBREAKDOWN", -6: "FE_EUNSUPPORTED"}
+
+
+class FeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class _Coef(ctypes.Structure):
+    _fields_ = [("n_modes", ctypes.c_int), ("modes", ctypes.POINTER(ctypes.c_int32)),
+                ("amp", ctypes.POINTER(ctypes.c_double)), ("phase", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("degree", ctypes.c_int), ("n", ctypes.c_int), ("geometry", ctypes.c_int),
+                ("deform_amp", ctypes.c_double), ("coef", _Coef), ("bc", ctypes.c_int), ("n_coarse", ctypes.c_int)]
+
+
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("nu_pre", ctypes.c_int),
+                ("nu_post", ctypes.c_int), ("smoother", ctypes.c_int), ("cheb_degree", ctypes.c_int),
+                ("cheb_ratio", ctypes.c_double), ("cheb_lmax", ctypes.c_double), ("omega", ctypes.c_double),
+                ("inner", ctypes.c_int), ("factors", ctypes.c_int), ("flexible", ctypes.c_int),
+                ("precond", ctypes.c_int)]
+
+
+class PcgReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("relres", ctypes.c_double),
+                ("energy0", ctypes.c_double), ("energy", ctypes.c_double), ("t_setup", ctypes.c_double),
+                ("t_solve", ctypes.c_double)]
+
+
+_vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "fe_problem_create": (_i, [ctypes.POINTER(_Desc), _vp, ctypes.POINTER(_vp)]),
+    "fe_problem_destroy": (None, [_vp]),
+    "fe_num_cells": (_i64, [_vp]),
+    "fe_cellvec_len": (_i64, [_vp]),
+    "fe_num_dofs": (_i64, [_vp]),
+    "fe_num_levels": (_i, [_vp]),
+    "fe_level_cells_1d": (_i, [_vp, _i]),
+    "fe_gather": (_i, [_vp, _vp, _vp, _i, _vp]),
+    "fe_assemble": (_i, [_vp, _vp, _vp, _i, _vp]),
+    "fe_dss": (_i, [_vp, _i, _vp, _i, _i, _vp]),
+    "fe_apply": (_i, [_vp, _vp, _vp, _i, _vp]),
+    "fe_apply_level": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
+    "patch_fdm_inverse": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
+    "patch_fdm_inverse_level": (_i, [_vp, _i, _vp, _vp, _i, _i, _vp]),
+    "fe_prolongate_add": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
+    "fe_restrict_residual": (_i, [_vp, _i, _vp, _vp, _vp, _i, _vp]),
+    "fe_jacobi_sweep": (_i, [_vp, _i, _vp, _vp, _vp, _d, _i, _i, _vp]),
+    "fe_rhs_manufactured": (_i, [_vp, _vp, _vp]),
+    "fe_dot": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d), _vp]),
+    "fe_assembled_norm2": (_i, [_vp, _vp, _i, ctypes.POINTER(_d), _vp]),
+    "fe_pcg_default_opts": (None, [ctypes.POINTER(PcgOpts)]),
+    "pcg_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _vp]),
+    "fe_vcycle": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), _i, _vp]),
+    "fe_estimate_lmax": (_i, [_vp, _i, _i, _i, _i, ctypes.POINTER(_d), _vp]),
+    "fe_prof_enable": (None, [_i]),
+    "fe_prof_reset": (None, []),
+    "fe_prof_query": (_i, [ctypes.c_char_p, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+    "fe_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(st):
+    if st != 0:
+        raise FeError(st, _lib.fe_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dt(t):
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("cell-wise tensors must be float64 or float32")
+
+
+def _ptr(t, n=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous device tensor" % name)
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d entries, expected %d" % (name, t.numel(), n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_opts(**kw):
+    o = PcgOpts()
+    _lib.fe_pcg_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """Owns an fe_problem handle (see include/fe.h)."""
+
+    def __init__(self, dim, degree, n, geometry=GEOM_CARTESIAN, bc=1, deform_amp=0.0, coef=None, n_coarse=0):
+        d = _Desc()
+        d.dim, d.degree, d.n, d.geometry = dim, degree, n, geometry
+        d.deform_amp, d.bc, d.n_coarse = deform_amp, bc, n_coarse
+        self._keep = []
+        if coef is not None:
+            modes, amps, phases = coef
+            m = np.ascontiguousarray(modes, dtype=np.int32)
+            a = np.ascontiguousarray(amps, dtype=np.float64)
+            ph = np.ascontiguousarray(phases, dtype=np.float64)
+            self._keep += [m, a, ph]
+            d.coef.n_modes = len(a)
+            d.coef.modes = m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            d.coef.amp = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.coef.phase = ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        _check(_lib.fe_problem_create(ctypes.byref(d), _stream(), ctypes.byref(h)))
+        self.h = h
+        self.dim, self.degree, self.n = dim, degree, n
+        self.K = degree + 1
+        self.n_cells = _lib.fe_num_cells(h)
+        self.len = _lib.fe_cellvec_len(h)
+        self.n_dofs = _lib.fe_num_dofs(h)
+        self.n_levels = _lib.fe_num_levels(h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.fe_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes
+    def level_n(self, level):
+        return _lib.fe_level_cells_1d(self.h, level)
+
+    def level_len(self, level):
+        n = self.level_n(level)
+        return n ** self.dim * self.K ** self.dim
+
+    def cellvec(self, dtype=torch.float64, level=-1):
+        ln = self.len if level == -1 else self.level_len(level)
+        return torch.zeros(ln, dtype=dtype, device="cuda")
+
+    # operations
+    def gather(self, xg, xc):
+        _check(_lib.fe_gather(self.h, _ptr(xg, self.n_dofs, "x_glob"), _ptr(xc, self.len, "x_cell"), _dt(xc),
+                              _stream()))
+
+    def assemble(self, yc, yg):
+        _check(_lib.fe_assemble(self.h, _ptr(yc, self.len, "y_cell"), _ptr(yg, self.n_dofs, "y_glob"), _dt(yc),
+                                _stream()))
+
+    def dss(self, v, averaging=False, level=-1):
+        _check(_lib.fe_dss(self.h, level, _ptr(v, name="v"), 1 if averaging else 0, _dt(v), _stream()))
+
+    def apply(self, x, y, level=-1):
+        _check(_lib.fe_apply_level(self.h, level, _ptr(x, name="x"), _ptr(y, name="y"), _dt(x), _stream()))
+
+    def patch_inverse(self, r, z, factors=0, level=-1):
+        _check(_lib.patch_fdm_inverse_level(self.h, level, _ptr(r, name="r"), _ptr(z, name="z"), _dt(r), factors,
+                                            _stream()))
+
+    def prolongate_add(self, fine_level, ec, ef):
+        _check(_lib.fe_prolongate_add(self.h, fine_level, _ptr(ec, name="e_coarse"), _ptr(ef, name="e_fine"),
+                                      _dt(ef), _stream()))
+
+    def restrict_residual(self, fine_level, bf, vf, bc):
+        _check(_lib.fe_restrict_residual(self.h, fine_level, _ptr(bf, name="b_fine"), _ptr(vf, name="v_fine"),
+                                         _ptr(bc, name="b_coarse"), _dt(bf), _stream()))
+
+    def jacobi_sweep(self, level, b, u, v, omega, u_is_zero=False):
+        _check(_lib.fe_jacobi_sweep(self.h, level, _ptr(b, name="b"), _ptr(u, name="u"), _ptr(v, name="v"),
+                                    float(omega), 1 if u_is_zero else 0, _dt(u), _stream()))
+
+    def rhs_manufactured(self, b):
+        _check(_lib.fe_rhs_manufactured(self.h, _ptr(b, self.len, "b"), _stream()))
+
+    def dot(self, a, b):
+        out = ctypes.c_double()
+        _check(_lib.fe_dot(self.h, _ptr(a, self.len, "a"), _ptr(b, self.len, "b"), _dt(a), ctypes.byref(out),
+                           _stream()))
+        return out.value
+
+    def assembled_norm2(self, r):
+        out = ctypes.c_double()
+        _check(_lib.fe_assembled_norm2(self.h, _ptr(r, self.len, "r"), _dt(r), ctypes.byref(out), _stream()))
+        return out.value
+
+    def vcycle(self, b, e, opts):
+        _check(_lib.fe_vcycle(self.h, _ptr(b, self.len, "b"), _ptr(e, self.len, "e"), ctypes.byref(opts), _dt(b),
+                              _stream()))
+
+    def estimate_lmax(self, level=-1, factors=0, steps=15):
+        out = ctypes.c_double()
+        _check(_lib.fe_estimate_lmax(self.h, level, SMOOTH_CHEB_FDM, factors, steps, ctypes.byref(out), _stream()))
+        return out.value
+
+    def pcg_solve(self, b, x, opts=None, raise_on_error=True):
+        if opts is None:
+            opts = default_opts()
+        rep = PcgReport()
+        st = _lib.pcg_solve(self.h, _ptr(b, self.len, "b"), _ptr(x, self.len, "x"), ctypes.byref(opts),
+                            ctypes.byref(rep), _stream())
+        if st != 0 and raise_on_error:
+            _check(st)
+        return {"status": STATUS.get(st, st), "iters": rep.iters, "converged": bool(rep.converged),
+                "relres": rep.relres, "energy0": rep.energy0, "energy": rep.energy, "t_setup": rep.t_setup,
+                "t_solve": rep.t_solve}
+
+
+def prof_enable(on=True):
+    _lib.fe_prof_enable(1 if on else 0)
+
+
+def prof_reset():
+    _lib.fe_prof_reset()
+
+
+def prof_query(name):
+    c, t = ctypes.c_int(), ctypes.c_double()
+    _check(_lib.fe_prof_query(name.encode(), ctypes.byref(c), ctypes.byref(t)))
+    return c.value, t.value
+
+
+def last_error():
+    return _lib.fe_last_error().decode()
