@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-step", action="store_true", help="time the headline step only (for profilers)")
+    ap.add_argument("--with-copy", action="store_true", help="with --only-step: add a plain copy kernel of known size")
     return ap.parse_args()
 
 
@@ -195,6 +196,14 @@ def main():
     kb = kernel_bytes(fe.Problem(3, 3, 2, bc=1), 8)  # shapes only
     P64 = None
     if args.only_step:
+        if args.with_copy:
+            # calibration for the HBM byte counters: a plain copy of a known size
+            # (2 x 134,217,728 bytes per launch) next to the kernels of the step
+            src = torch.ones(16777216, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(5):
+                dst.copy_(src)
+            torch.cuda.synchronize()
         print(json.dumps(main64))
         return
     log("Q3 64^3 FP32 step")

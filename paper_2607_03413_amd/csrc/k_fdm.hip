@@ -50,44 +50,125 @@ __device__ __forceinline__ EigPtrs<T, M> eig_ptrs(const T* __restrict__ eig, int
   return e;
 }
 
+// Copies of patch-local node offset o (1 <= o <= 2k-1) along one axis: cell
+// slot 0 or 1 of the patch and the local index in that cell, lower slot first.
+template <int K>
+__device__ __forceinline__ AxisCopies patch_axis_copies(int o) {
+  constexpr int k = K - 1;
+  AxisCopies a;
+  if (o < k) { a.cnt = 1; a.c[0] = 0; a.i[0] = o; }
+  else if (o > k) { a.cnt = 1; a.c[0] = 1; a.i[0] = o - k; }
+  else { a.cnt = 2; a.c[0] = 0; a.i[0] = k; a.c[1] = 1; a.i[1] = 0; }
+  if (a.cnt == 1) { a.c[1] = a.c[0]; a.i[1] = a.i[0]; }
+  return a;
+}
+
+// Thread layout of kernel (1) in 3D.  A patch is handled by M^2 threads, one
+// z-pencil each.  When a patch fits in one wavefront (M^2 <= 64), PPW
+// patches share a wavefront and never straddle two, so the pencil
+// re-orientations through LDS only need wavefront-level ordering; otherwise
+// a patch spans several wavefronts and the block synchronizes.
+template <int K>
+struct PatchLayout {
+  static constexpr int k = K - 1;
+  static constexpr int M = 2 * k - 1;
+  static constexpr int TPP = M * M;
+  static constexpr bool WAVE = TPP <= 64;
+  static constexpr int PPW = WAVE ? 64 / TPP : 0;
+  static constexpr int PPB = WAVE ? 4 * PPW : (256 / TPP > 0 ? 256 / TPP : 1);
+  static constexpr int THREADS = WAVE ? 256 : PPB * TPP;
+};
+
+template <bool WAVE>
+__device__ __forceinline__ void patch_sync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Kernel (1), 3D.  A block owns PPB consecutive patches of one x-row
+// (fixed vy, vz).  Their 2^3 cells form four contiguous runs of PPB+1 cells
+// (cy in {vy-1, vy}, cz in {vz-1, vz}), which are first copied to LDS with
+// coalesced loads; the patch residuals are then assembled from LDS.
 template <typename T, int K, bool PER_PATCH>
 __global__ void __launch_bounds__(256) k_fdm_patch3(const T* __restrict__ r, T* __restrict__ W,
-                                                    const T* __restrict__ eig, T scale, int n,
-                                                    int64_t n_patches) {
-  constexpr int k = K - 1;
-  constexpr int M = 2 * k - 1;
-  constexpr int TPP = M * M;
-  constexpr int PPB = 256 / TPP > 0 ? 256 / TPP : 1;
+                                                    const T* __restrict__ eig, T scale, int n, int segs) {
+  using PL = PatchLayout<K>;
+  constexpr int k = PL::k, M = PL::M, TPP = PL::TPP, PPB = PL::PPB;
+  constexpr bool WAVE = PL::WAVE;
   constexpr int RS = M + 1;
   constexpr int PS = M * RS;
   constexpr int CS = M * PS;
+  constexpr int K3 = K * K * K;
+  constexpr int NCX = PPB + 1;
+  __shared__ T sc[4 * NCX * K3];
   __shared__ T sl[PPB * CS];
   const int tid = threadIdx.x;
-  const int c = tid / TPP;
-  const int p = tid - c * TPP;
-  const int p0 = p % M, p1 = p / M;
-  const int64_t pid = (int64_t)blockIdx.x * PPB + c;
-  const bool active = pid < n_patches;
-  const int nv = n - 1;
-  int vx = 1, vy = 1, vz = 1;
-  if (active) {
-    vx = 1 + (int)(pid % nv);
-    const int64_t t = pid / nv;
-    vy = 1 + (int)(t % nv);
-    vz = 1 + (int)(t / nv);
+  int c, p;
+  bool lane_ok = true;
+  if (WAVE) {
+    const int w = tid >> 6, lane = tid & 63;
+    lane_ok = lane < PL::PPW * TPP;
+    // surplus lanes shadow pencil 0 of the wave's first patch: identical values, no global store
+    c = w * PL::PPW + (lane_ok ? lane / TPP : 0);
+    p = lane_ok ? lane % TPP : 0;
+  } else {
+    c = tid / TPP;
+    p = tid - c * TPP;
   }
-  const EigPtrs<T, M> E = eig_ptrs<T, M, PER_PATCH>(eig, active ? pid : 0);
+  const int p0 = p % M, p1 = p / M;
+  const int nv = n - 1;
+  const int seg = blockIdx.x % segs;
+  const int row = blockIdx.x / segs;
+  const int vy = 1 + row % nv, vz = 1 + row / nv;
+  const int vx0 = 1 + seg * PPB;
+  const int npatch = min(PPB, nv - (vx0 - 1));
+  const int ncells = npatch + 1;
+  // stage the four runs of cells
+  for (int q = 0; q < 4; ++q) {
+    const int cy = vy - 1 + (q & 1), cz = vz - 1 + (q >> 1);
+    const T* src = r + ((int64_t)(vx0 - 1) + (int64_t)n * (cy + (int64_t)n * cz)) * K3;
+    T* dst = sc + q * NCX * K3;
+    for (int i = tid; i < ncells * K3; i += blockDim.x) dst[i] = src[i];
+  }
+  // per-patch eigen-data of the block's patches (contiguous in pid) is staged too
+  constexpr int EP = 3 * M * M + 3 * M;
+  __shared__ T se[PER_PATCH ? PPB * EP : 1];
+  const int64_t pid0 = (int64_t)(vx0 - 1) + (int64_t)nv * ((vy - 1) + (int64_t)nv * (vz - 1));
+  if (PER_PATCH) {
+    const T* src = eig + pid0 * EP;
+    for (int i = tid; i < npatch * EP; i += blockDim.x) se[i] = src[i];
+  }
+  __syncthreads();
+  const bool active = c < npatch;
+  const int64_t pid = active ? pid0 + c : 0;
+  const EigPtrs<T, M> E = PER_PATCH ? eig_ptrs<T, M, true>(se, active ? c : 0) : eig_ptrs<T, M, false>(eig, 0);
   T* ls = sl + c * CS;
   T v[M], t[M];
 
-  // (a) gather the assembled residual on the z-pencil (a = p0, b = p1)
+  // (a) assemble the residual on the z-pencil (a = p0, b = p1) from LDS, cascade order
   if (active) {
-    const AxisCopies ax = axis_copies<K>(k * (vx - 1) + p0 + 1, n);
-    const AxisCopies ay = axis_copies<K>(k * (vy - 1) + p1 + 1, n);
+    const AxisCopies ax = patch_axis_copies<K>(p0 + 1);
+    const AxisCopies ay = patch_axis_copies<K>(p1 + 1);
 #pragma unroll
     for (int cz = 0; cz < M; ++cz) {
-      const AxisCopies az = axis_copies<K>(k * (vz - 1) + cz + 1, n);
-      v[cz] = cascade_sum<T, K, 3>(r, ax, ay, az, n);
+      const AxisCopies az = patch_axis_copies<K>(cz + 1);
+      T zs[2];
+      for (int sz = 0; sz < az.cnt; ++sz) {
+        T ys[2];
+        for (int sy = 0; sy < ay.cnt; ++sy) {
+          const T* base = sc + ((az.c[sz] * 2 + ay.c[sy]) * NCX + c) * K3 + K * (ay.i[sy] + K * az.i[sz]);
+          T xs = base[ax.c[0] * K3 + ax.i[0]];
+          if (ax.cnt == 2) xs += base[ax.c[1] * K3 + ax.i[1]];
+          ys[sy] = xs;
+        }
+        zs[sz] = ay.cnt == 2 ? ys[0] + ys[1] : ys[0];
+      }
+      v[cz] = az.cnt == 2 ? zs[0] + zs[1] : zs[0];
     }
   } else {
 #pragma unroll
@@ -97,15 +178,15 @@ __global__ void __launch_bounds__(256) k_fdm_patch3(const T* __restrict__ r, T* 
   pencil_mtv<T, M>(E.Sz, v, t);
 #pragma unroll
   for (int cz = 0; cz < M; ++cz) ls[cz * PS + p1 * RS + p0] = t[cz];
-  __syncthreads();
+  patch_sync<WAVE>();
   // (c) S_y^T along y: thread (a = p0, cz = p1)
 #pragma unroll
   for (int j = 0; j < M; ++j) v[j] = ls[p1 * PS + j * RS + p0];
   pencil_mtv<T, M>(E.Sy, v, t);
-  __syncthreads();
+  patch_sync<WAVE>();
 #pragma unroll
   for (int b = 0; b < M; ++b) ls[p1 * PS + b * RS + p0] = t[b];
-  __syncthreads();
+  patch_sync<WAVE>();
   // (d) x-pencil (b = p0, cz = p1): S_x^T, divide, S_x
 #pragma unroll
   for (int j = 0; j < M; ++j) v[j] = ls[p1 * PS + p0 * RS + j];
@@ -116,23 +197,23 @@ __global__ void __launch_bounds__(256) k_fdm_patch3(const T* __restrict__ r, T* 
     for (int a = 0; a < M; ++a) t[a] = t[a] * scale / (E.lx[a] + lyz);
   }
   pencil_mv<T, M>(E.Sx, t, v);
-  __syncthreads();
+  patch_sync<WAVE>();
 #pragma unroll
   for (int a = 0; a < M; ++a) ls[p1 * PS + p0 * RS + a] = v[a];
-  __syncthreads();
+  patch_sync<WAVE>();
   // (e) S_y along y: thread (a = p0, cz = p1)
 #pragma unroll
   for (int j = 0; j < M; ++j) v[j] = ls[p1 * PS + j * RS + p0];
   pencil_mv<T, M>(E.Sy, v, t);
-  __syncthreads();
+  patch_sync<WAVE>();
 #pragma unroll
   for (int b = 0; b < M; ++b) ls[p1 * PS + b * RS + p0] = t[b];
-  __syncthreads();
+  patch_sync<WAVE>();
   // (f) S_z along z: thread (a = p0, b = p1); write the patch solution
 #pragma unroll
   for (int j = 0; j < M; ++j) v[j] = ls[j * PS + p1 * RS + p0];
   pencil_mv<T, M>(E.Sz, v, t);
-  if (active) {
+  if (active && lane_ok) {
     T* w = W + pid * (M * M * M) + p1 * M + p0;
 #pragma unroll
     for (int cz = 0; cz < M; ++cz) w[cz * M * M] = t[cz];
@@ -265,6 +346,100 @@ __global__ void __launch_bounds__(256) k_fdm_sum(const T* __restrict__ W, T* __r
   z[e] = s;
 }
 
+// Kernel (2), 3D, staged: a block owns TXC consecutive cells of one x-row
+// (fixed cy, cz).  The patches touching them have vy in {cy, cy+1}, vz in
+// {cz, cz+1} and vx in [cx0, cx0+TXC]; for each (vy, vz) their solutions
+// are one contiguous run of the patch-major buffer, copied to LDS with
+// coalesced loads.  Each entry then sums its (at most 8) contributions in
+// the fixed order (vz, vy, vx ascending), which depends only on the node.
+template <int K>
+struct SumTile {
+  static constexpr int k = K - 1;
+  static constexpr int M = 2 * k - 1;
+  static constexpr int K3 = K * K * K;
+  static constexpr int M3 = M * M * M;
+  static constexpr int TXC = (512 / K3) > 0 ? (512 / K3) : 1;
+};
+
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_fdm_sum3_staged(const T* __restrict__ W, T* __restrict__ z, int n,
+                                                         int segs) {
+  using TL = SumTile<K>;
+  constexpr int k = TL::k, M = TL::M, K3 = TL::K3, M3 = TL::M3, TXC = TL::TXC;
+  constexpr int NPX = TXC + 1;
+  __shared__ T sw[4 * NPX * M3];
+  const int nv = n - 1;
+  const int seg = blockIdx.x % segs;
+  const int row = blockIdx.x / segs;
+  const int cy = row % n, cz = row / n;
+  const int cx0 = seg * TXC;
+  const int ncell = min(TXC, n - cx0);
+  // patch runs: vx in [vlo, vhi]
+  const int vlo = max(cx0, 1), vhi = min(cx0 + ncell, nv);
+  const int npx = vhi - vlo + 1;   // may be <= 0 when n == 1
+  for (int q = 0; q < 4; ++q) {
+    const int vy = cy + (q & 1), vz = cz + (q >> 1);
+    if (vy < 1 || vy > nv || vz < 1 || vz > nv || npx <= 0) continue;
+    const T* src = W + ((int64_t)(vlo - 1) + (int64_t)nv * ((vy - 1) + (int64_t)nv * (vz - 1))) * M3;
+    T* dst = sw + q * NPX * M3;
+    for (int i = threadIdx.x; i < npx * M3; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ncell * K3; e += blockDim.x) {
+    const int cl = e / K3;
+    const int loc = e - cl * K3;
+    const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+    const int cx = cx0 + cl;
+    const AxisPatches px = axis_patches<K>(k * cx + ix, n);
+    const AxisPatches py = axis_patches<K>(k * cy + iy, n);
+    const AxisPatches pz = axis_patches<K>(k * cz + iz, n);
+    T s = T(0);
+    for (int a = 0; a < pz.cnt; ++a)
+      for (int b = 0; b < py.cnt; ++b) {
+        const int q = (pz.v[a] - cz) * 2 + (py.v[b] - cy);
+        const T* base = sw + q * NPX * M3 + M * (py.o[b] + M * pz.o[a]);
+        for (int c = 0; c < px.cnt; ++c) s += base[(px.v[c] - vlo) * M3 + px.o[c]];
+      }
+    z[((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc] = s;
+  }
+}
+
+// Kernel (2), 3D, node-centric: one thread per global node sums the patch
+// solutions at that node (each value of the patch-major buffer is read
+// exactly once, consecutive threads read consecutive patch entries) in the
+// order (vz, vy, vx ascending), and writes the sum to every cell copy.
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_fdm_sum_nodes3(const T* __restrict__ W, T* __restrict__ z, int n,
+                                                        int64_t n_nodes) {
+  constexpr int k = K - 1;
+  constexpr int M = 2 * k - 1;
+  constexpr int M3 = M * M * M;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_nodes) return;
+  const int N = k * n + 1;
+  const int gx = (int)(g % N);
+  const int64_t t = g / N;
+  const int gy = (int)(t % N), gz = (int)(t / N);
+  const int nv = n - 1;
+  const AxisPatches px = axis_patches<K>(gx, n), py = axis_patches<K>(gy, n), pz = axis_patches<K>(gz, n);
+  T s = T(0);
+  for (int a = 0; a < pz.cnt; ++a)
+    for (int b = 0; b < py.cnt; ++b) {
+      const int64_t rowp = (int64_t)nv * ((py.v[b] - 1) + (int64_t)nv * (pz.v[a] - 1));
+      const int off = M * (py.o[b] + M * pz.o[a]);
+      for (int c = 0; c < px.cnt; ++c) s += W[(rowp + px.v[c] - 1) * M3 + off + px.o[c]];
+    }
+  const AxisCopies ax = axis_copies<K>(gx, n), ay = axis_copies<K>(gy, n), az = axis_copies<K>(gz, n);
+  for (int sz = 0; sz < az.cnt; ++sz)
+    for (int sy = 0; sy < ay.cnt; ++sy)
+      for (int sx = 0; sx < ax.cnt; ++sx) z[copy_addr<K, 3>(ax, ay, az, sx, sy, sz, n)] = s;
+}
+
+template <int K, typename T>
+constexpr bool sum_staged_fits() {
+  return 4 * (SumTile<K>::TXC + 1) * SumTile<K>::M3 * sizeof(T) <= 64 * 1024;
+}
+
 size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt) {
   const Level& L = level_of(p, level);
   const int64_t nv = L.n - 1;
@@ -282,18 +457,21 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
   if (p->dim == 3) {
     const int64_t np = nv * nv * nv;
     if (np > 0) {
-      constexpr int PPB = 256 / (M * M) > 0 ? 256 / (M * M) : 1;
-      const unsigned nb = (unsigned)((np + PPB - 1) / PPB);
+      constexpr int PPB = PatchLayout<K>::PPB;
+      constexpr int THREADS = PatchLayout<K>::THREADS;
+      const int segs = (int)((nv + PPB - 1) / PPB);
+      const unsigned nb = (unsigned)(segs * nv * nv);
       ProfScope ps("fdm_patch", s);
       if (per_patch)
-        hipLaunchKernelGGL((k_fdm_patch3<T, K, true>), dim3(nb), dim3(PPB * M * M), 0, s, r, W, eig, scale, L.n, np);
+        hipLaunchKernelGGL((k_fdm_patch3<T, K, true>), dim3(nb), dim3(THREADS), 0, s, r, W, eig, scale, L.n, segs);
       else
-        hipLaunchKernelGGL((k_fdm_patch3<T, K, false>), dim3(nb), dim3(PPB * M * M), 0, s, r, W, eig, scale, L.n, np);
+        hipLaunchKernelGGL((k_fdm_patch3<T, K, false>), dim3(nb), dim3(THREADS), 0, s, r, W, eig, scale, L.n, segs);
       FE_HIP_CHECK(hipGetLastError());
     }
     ProfScope ps2("fdm_sum", s);
-    hipLaunchKernelGGL((k_fdm_sum<T, K, 3>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
-                       L.len);
+    const int64_t N = (int64_t)(K - 1) * L.n + 1;
+    const int64_t nn = N * N * N;
+    hipLaunchKernelGGL((k_fdm_sum_nodes3<T, K>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, W, z, L.n, nn);
   } else {
     const int64_t np = nv * nv;
     if (np > 0) {

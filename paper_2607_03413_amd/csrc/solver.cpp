@@ -353,7 +353,8 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
   fe_pcg_report R{};
   fe_status result = FE_OK;
   int it = 0;
-  if (!std::isfinite(relres)) result = fail(FE_EBREAKDOWN, "non-finite right-hand side or initial residual");
+  if (!std::isfinite(nb2) || !std::isfinite(relres))
+    result = fail(FE_EBREAKDOWN, "non-finite right-hand side or initial residual");
   if (result == FE_OK && relres > o->tol) {
     FE_CHECK(precondition(p, r, z, s));
     FE_CHECK(launch_cast(n, z, FE_F64, pv, FE_F64, s));
