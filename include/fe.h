@@ -217,6 +217,53 @@ fe_status fe_vcycle(fe_problem* prob, const void* b_cell, void* e_cell, const fe
 fe_status fe_estimate_lmax(fe_problem* prob, int level, int smoother, int factors, int steps,
                            double* out, void* stream);
 
+/* ---- Learned per-patch factors (deformed geometry; factors = 2 above) ----
+ * The paper's admissible smoother class (eq. precond_consistency) admits any
+ * patch solver; on the deformed mesh the separable surrogate
+ *   A_sep = Kx (x) My (x) Mz + Mx (x) Ky (x) Mz + Mx (x) My (x) Kz
+ * has 12 weights per patch (alpha_{d,c} scale D on interval c of axis d in
+ * K_d, beta_{d,c} scale B in M_d), stored as
+ *   [alpha_x0, alpha_x1, alpha_y0, alpha_y1, alpha_z0, alpha_z1, beta_x0, ..., beta_z1].
+ * A 64 -> 64 -> 64 -> 12 MLP (tanh, FP32) predicts their normalized logs
+ * t = P(log w - log(h)/3) (P removes the 3 scaling gauges) from 64 patch
+ * features.  All arrays are DEVICE pointers, row-major, one row per patch
+ * (patch index (vx-1) + (n-1)((vy-1) + (n-1)(vz-1)), interior vertices). */
+
+int fe_mlp_num_params(void);                                  /* 9100 */
+int64_t fe_num_patches(const fe_problem* prob, int level);    /* (n_l - 1)^d */
+
+/* Features (FP64, n_patches x 64): per cell slot s = sx + 2 sy + 4 sz, the
+ * entries (xx, yy, zz, xy, xz, yz) of n kappa det(J) J^-1 J^-T at the cell
+ * centre, log kappa and log(n^3 det J) there. */
+fe_status fe_patch_features(fe_problem* prob, int level, double* feats, void* stream);
+
+/* C[p][i + 4 j + 16 l] = <A_p, E_l (x) E_j (x) E_i>_F, E in {D on interval 0,
+ * D on interval 1, B on 0, B on 1} (FP64, n_patches x 64), from the metric. */
+fe_status fe_patch_inner_tensor(fe_problem* prob, int level, double* C, void* stream);
+
+/* Training targets (FP64, n_patches x 12): normalized log-weights of the best
+ * Kronecker-sum fit min ||A_p - A_sep(w)||_F by `sweeps` sweeps of alternating
+ * least squares (stiffness weights, then masses of x, y, z) from the
+ * averaged-geometry weights. */
+fe_status fe_patch_fit_targets(fe_problem* prob, int level, int sweeps, double* targets, void* stream);
+
+/* Model parameters (FP32, fe_mlp_num_params() values: W1 64x64, b1, W2 64x64,
+ * b2, W3 12x64, b3; W row-major [out][in]).  set_params also resets Adam. */
+fe_status fe_mlp_set_params(fe_problem* prob, const float* params, void* stream);
+fe_status fe_mlp_get_params(const fe_problem* prob, float* params, void* stream);
+/* Y (n x 12) = model(X (n x 64)), FP32. */
+fe_status fe_mlp_forward(fe_problem* prob, const float* X, float* Y, int n, void* stream);
+/* Mean squared error over the n x 12 outputs and its gradient (FP32, same layout as the parameters). */
+fe_status fe_mlp_loss_grad(fe_problem* prob, const float* X, const float* T, int n, float* grad, double* loss,
+                           void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the given gradient. */
+fe_status fe_mlp_adam_step(fe_problem* prob, const float* grad, double lr, void* stream);
+/* Minibatch Adam training: `epochs` passes over a permutation of the n rows
+ * (splitmix64 shuffle from `seed`), batches of `batch` rows (the last partial
+ * batch is dropped).  final_loss: mean loss of the last epoch.  Synchronous. */
+fe_status fe_mlp_train(fe_problem* prob, const float* X, const float* T, int n, int epochs, int batch, double lr,
+                       uint64_t seed, double* final_loss, void* stream);
+
 /* Per-kernel timing with HIP events on the launch stream (tracing aid).
  * enable = 1 starts recording, 0 stops; reset clears.  fe_prof_query
  * synchronizes and returns, for kernel family `name`, the number of launches

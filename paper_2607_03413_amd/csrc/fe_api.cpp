@@ -131,6 +131,10 @@ fe_status fe_problem_create(const fe_problem_desc* desc, void* stream, fe_proble
   if (desc->geometry == FE_GEOM_DEFORMED && desc->dim != 3)
     return fail(FE_EUNSUPPORTED, "deformed geometry is implemented for d = 3");
   if (desc->bc != 0 && desc->bc != 1) return fail(FE_EINVAL, "bc must be 0 or 1");
+  // det of x + amp prod sin(2 pi x_b) (1,1,1) is 1 + 2 pi amp (c s s + s c s + s s c), whose
+  // bracket ranges over [-2/sqrt(3), 2/sqrt(3)]: the map folds for |amp| >= sqrt(3) / (4 pi)
+  if (desc->geometry == FE_GEOM_DEFORMED && !(std::fabs(desc->deform_amp) < std::sqrt(3.0) / (4.0 * M_PI)))
+    return fail(FE_EINVAL, "deformation amplitude folds the mesh (|amp| must be < sqrt(3)/(4 pi))");
   {
     const int64_t K = desc->degree + 1;
     int64_t len = K * K * (int64_t)desc->n * desc->n;

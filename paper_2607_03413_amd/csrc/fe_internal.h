@@ -122,6 +122,7 @@ struct fe_problem {
   // learned-factor MLP (see fe_mlp_*)
   fe::DeviceBuf mlp_params, mlp_adam_m, mlp_adam_v;
   int mlp_ready = 0;
+  int64_t mlp_step = 0;
 };
 
 namespace fe {
@@ -165,6 +166,8 @@ fe_status launch_coarse_solve(const fe_problem* p, const void* b0, void* e0, fe_
 fe_status launch_average_convert(const fe_problem* p, int level, const double* r, void* out, fe_dtype dt,
                                  hipStream_t s);
 fe_status launch_mask_boundary(const fe_problem* p, int level, void* v, fe_dtype dt, hipStream_t s);
+fe_status launch_jacobi_avg(const fe_problem* p, int level, const void* u, const void* b, const void* v,
+                            const void* dinv, void* out, double omega, int u_is_zero, fe_dtype dt, hipStream_t s);
 fe_status launch_make_dinv(const fe_problem* p, int level, const double* d, void* dinv, fe_dtype dt, hipStream_t s);
 fe_status launch_diag_cartesian(const fe_problem* p, int level, void* d, fe_dtype dt, hipStream_t s);
 fe_status launch_diag_general(const fe_problem* p, int level, void* d, fe_dtype dt, hipStream_t s);

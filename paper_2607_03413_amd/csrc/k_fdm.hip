@@ -213,11 +213,72 @@ __global__ void __launch_bounds__(256) k_fdm_patch3(const T* __restrict__ r, T* 
 #pragma unroll
   for (int j = 0; j < M; ++j) v[j] = ls[j * PS + p1 * RS + p0];
   pencil_mv<T, M>(E.Sz, v, t);
+  // Write the solution split by cell slot: slot s = sx + 2 sy + 4 sz of the
+  // patch holds the k^3 patch nodes inside that cell (offset o <= k in slot 0
+  // at j = o - 1, o >= k in slot 1 at j = o - k; the node o = k is in both).
+  // Each patch fills 8 k^3 contiguous values; each cell later reads one
+  // contiguous k^3 block per corner.
   if (active && lane_ok) {
-    T* w = W + pid * (M * M * M) + p1 * M + p0;
+    constexpr int k3 = k * k * k;
+    T* wp = W + pid * (8 * k3);
+    const int ox = p0 + 1, oy = p1 + 1;
+    for (int sy = 0; sy < 2; ++sy) {
+      const int jy = sy ? oy - k : oy - 1;
+      if (jy < 0 || jy >= k) continue;
+      for (int sx = 0; sx < 2; ++sx) {
+        const int jx = sx ? ox - k : ox - 1;
+        if (jx < 0 || jx >= k) continue;
 #pragma unroll
-    for (int cz = 0; cz < M; ++cz) w[cz * M * M] = t[cz];
+        for (int cz = 0; cz < M; ++cz) {
+          const int oz = cz + 1;
+          if (oz <= k) wp[(sx + 2 * sy) * k3 + jx + k * (jy + k * (oz - 1))] = t[cz];
+          if (oz >= k) wp[(sx + 2 * sy + 4) * k3 + jx + k * (jy + k * (oz - k))] = t[cz];
+        }
+      }
+    }
   }
+}
+
+// Kernel (2), 3D: one thread per cell-wise entry sums the contributions of the
+// patches at the cell's (up to 8) corners from the slot-split buffer, in the
+// order bz, by, bx ascending (= patch vertices ascending, the same for every
+// copy of a node, so copies come out bit-identical), and writes its own entry:
+// consecutive threads write consecutive addresses, whole cache lines.
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_fdm_sum_slots3(const T* __restrict__ W, T* __restrict__ z, int n,
+                                                        int64_t len) {
+  constexpr int k = K - 1;
+  constexpr int k3 = k * k * k;
+  constexpr int K3 = K * K * K;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const int64_t cell = e / K3;
+  const int loc = (int)(e - cell * K3);
+  const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+  const int cx = (int)(cell % n);
+  const int64_t t = cell / n;
+  const int cy = (int)(t % n), cz = (int)(t / n);
+  const int nv = n - 1;
+  T s = T(0);
+#pragma unroll
+  for (int bz = 0; bz < 2; ++bz) {
+    const int vz = cz + bz, jz = iz - bz;
+    if (vz < 1 || vz > nv || jz < 0 || jz >= k) continue;
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      const int vy = cy + by, jy = iy - by;
+      if (vy < 1 || vy > nv || jy < 0 || jy >= k) continue;
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const int vx = cx + bx, jx = ix - bx;
+        if (vx < 1 || vx > nv || jx < 0 || jx >= k) continue;
+        const int64_t pid = (vx - 1) + (int64_t)nv * ((vy - 1) + (int64_t)nv * (vz - 1));
+        const int slot = (1 - bx) + 2 * (1 - by) + 4 * (1 - bz);
+        s += W[pid * (8 * k3) + slot * k3 + jx + k * (jy + k * jz)];
+      }
+    }
+  }
+  z[e] = s;
 }
 
 template <typename T, int K, bool PER_PATCH>
@@ -444,8 +505,10 @@ size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt) {
   const Level& L = level_of(p, level);
   const int64_t nv = L.n - 1;
   const int64_t M = 2 * p->k - 1;
+  const int64_t k = p->k;
   const int64_t np = p->dim == 3 ? nv * nv * nv : nv * nv;
-  const int64_t mp = p->dim == 3 ? M * M * M : M * M;
+  // 3D: slot-split layout, 8 k^3 per patch; 2D: patch-major, M^2 per patch
+  const int64_t mp = p->dim == 3 ? 8 * k * k * k : M * M;
   return (size_t)(np * mp) * (dt == FE_F64 ? 8 : 4);
 }
 
@@ -469,9 +532,8 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
       FE_HIP_CHECK(hipGetLastError());
     }
     ProfScope ps2("fdm_sum", s);
-    const int64_t N = (int64_t)(K - 1) * L.n + 1;
-    const int64_t nn = N * N * N;
-    hipLaunchKernelGGL((k_fdm_sum_nodes3<T, K>), dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, W, z, L.n, nn);
+    hipLaunchKernelGGL((k_fdm_sum_slots3<T, K>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
+                       L.len);
   } else {
     const int64_t np = nv * nv;
     if (np > 0) {

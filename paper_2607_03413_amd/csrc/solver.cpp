@@ -159,8 +159,10 @@ static fe_status jacobi_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe
   for (int it = 0; it < sweeps; ++it) {
     const bool z = u_zero && it == 0;
     if (!z) FE_CHECK(launch_apply(p, l, L.e[di].p, L.v[di].p, dt, s));
-    FE_CHECK(launch_jacobi_update(p, l, L.b[di].p, L.v[di].p, L.e[di].p, dinv, omega, z ? 1 : 0, dt, s));
-    FE_CHECK(launch_dss(p, l, L.e[di].p, 1, dt, s));
+    // fused update + averaging DSS into t, then t becomes the iterate
+    FE_CHECK(launch_jacobi_avg(p, l, L.e[di].p, L.b[di].p, L.v[di].p, dinv, L.t[di].p, omega, z ? 1 : 0, dt, s));
+    std::swap(L.e[di].p, L.t[di].p);
+    std::swap(L.e[di].bytes, L.t[di].bytes);
   }
   return FE_OK;
 }

@@ -82,6 +82,17 @@ _SIGS = {
     "pcg_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _vp]),
     "fe_vcycle": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), _i, _vp]),
     "fe_estimate_lmax": (_i, [_vp, _i, _i, _i, _i, ctypes.POINTER(_d), _vp]),
+    "fe_mlp_num_params": (_i, []),
+    "fe_num_patches": (_i64, [_vp, _i]),
+    "fe_patch_features": (_i, [_vp, _i, _vp, _vp]),
+    "fe_patch_inner_tensor": (_i, [_vp, _i, _vp, _vp]),
+    "fe_patch_fit_targets": (_i, [_vp, _i, _i, _vp, _vp]),
+    "fe_mlp_set_params": (_i, [_vp, _vp, _vp]),
+    "fe_mlp_get_params": (_i, [_vp, _vp, _vp]),
+    "fe_mlp_forward": (_i, [_vp, _vp, _vp, _i, _vp]),
+    "fe_mlp_loss_grad": (_i, [_vp, _vp, _vp, _i, _vp, ctypes.POINTER(_d), _vp]),
+    "fe_mlp_adam_step": (_i, [_vp, _vp, _d, _vp]),
+    "fe_mlp_train": (_i, [_vp, _vp, _vp, _i, _i, _i, _d, ctypes.c_uint64, ctypes.POINTER(_d), _vp]),
     "fe_prof_enable": (None, [_i]),
     "fe_prof_reset": (None, []),
     "fe_prof_query": (_i, [ctypes.c_char_p, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
@@ -235,6 +246,56 @@ class Problem:
         _check(_lib.fe_estimate_lmax(self.h, level, SMOOTH_CHEB_FDM, factors, steps, ctypes.byref(out), _stream()))
         return out.value
 
+    # learned per-patch factors
+    def num_patches(self, level=-1):
+        return _lib.fe_num_patches(self.h, level)
+
+    def patch_features(self, level=-1):
+        out = torch.empty(max(self.num_patches(level), 1) * 64, dtype=torch.float64, device="cuda")
+        _check(_lib.fe_patch_features(self.h, level, _ptr(out), _stream()))
+        return out[: self.num_patches(level) * 64].view(-1, 64)
+
+    def patch_inner_tensor(self, level=-1):
+        out = torch.empty(max(self.num_patches(level), 1) * 64, dtype=torch.float64, device="cuda")
+        _check(_lib.fe_patch_inner_tensor(self.h, level, _ptr(out), _stream()))
+        return out[: self.num_patches(level) * 64].view(-1, 64)
+
+    def patch_fit_targets(self, level=-1, sweeps=30):
+        out = torch.empty(max(self.num_patches(level), 1) * 12, dtype=torch.float64, device="cuda")
+        _check(_lib.fe_patch_fit_targets(self.h, level, sweeps, _ptr(out), _stream()))
+        return out[: self.num_patches(level) * 12].view(-1, 12)
+
+    def mlp_set_params(self, params):
+        _check(_lib.fe_mlp_set_params(self.h, _ptr(params, MLP_PARAMS, "params"), _stream()))
+
+    def mlp_get_params(self):
+        out = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        _check(_lib.fe_mlp_get_params(self.h, _ptr(out), _stream()))
+        return out
+
+    def mlp_forward(self, X):
+        X = X.float().contiguous()
+        Y = torch.empty(X.shape[0], 12, dtype=torch.float32, device="cuda")
+        _check(_lib.fe_mlp_forward(self.h, _ptr(X), _ptr(Y), X.shape[0], _stream()))
+        return Y
+
+    def mlp_loss_grad(self, X, T):
+        X, T = X.float().contiguous(), T.float().contiguous()
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        loss = ctypes.c_double()
+        _check(_lib.fe_mlp_loss_grad(self.h, _ptr(X), _ptr(T), X.shape[0], _ptr(g), ctypes.byref(loss), _stream()))
+        return loss.value, g
+
+    def mlp_adam_step(self, grad, lr=1e-3):
+        _check(_lib.fe_mlp_adam_step(self.h, _ptr(grad, MLP_PARAMS, "grad"), float(lr), _stream()))
+
+    def mlp_train(self, X, T, epochs, batch=256, lr=1e-3, seed=0):
+        X, T = X.float().contiguous(), T.float().contiguous()
+        loss = ctypes.c_double()
+        _check(_lib.fe_mlp_train(self.h, _ptr(X), _ptr(T), X.shape[0], epochs, batch, float(lr), seed,
+                                 ctypes.byref(loss), _stream()))
+        return loss.value
+
     def pcg_solve(self, b, x, opts=None, raise_on_error=True):
         if opts is None:
             opts = default_opts()
@@ -264,3 +325,6 @@ def prof_query(name):
 
 def last_error():
     return _lib.fe_last_error().decode()
+
+
+MLP_PARAMS = _lib.fe_mlp_num_params()

@@ -97,3 +97,11 @@ def test_deformed_pcg_matches_sparse_solve(gpu_lib, smoother, inner, flexible):
     xe = np.zeros(m.n_global)
     xe[I] = spla.spsolve(A[I][:, I].tocsc(), bg[I])
     assert relerr(host(x), m.gather(xe).ravel()) < 1e-7
+
+
+def test_folding_deformation_is_rejected(gpu_lib):
+    fe = gpu_lib
+    with pytest.raises(fe.FeError):
+        problem_amp = fe.Problem(3, 2, 4, geometry=fe.GEOM_DEFORMED, deform_amp=0.15)
+        del problem_amp
+    fe.Problem(3, 2, 4, geometry=fe.GEOM_DEFORMED, deform_amp=0.137).close()

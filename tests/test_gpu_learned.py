@@ -1,0 +1,108 @@
+"""GPU parity of the learned-factor path: features, inner tensor, best-fit targets, MLP
+forward / gradient / Adam, and what the trained model gains in the MG-PCG solve."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.geometry import DeformedGeometry
+from oracle.learned import (N_PARAMS, adam_step, fit_targets, forward, loss_and_grad, patch_features,
+                            pieces_1d)
+from oracle.mesh import StructuredMesh
+from oracle.operators import assemble_csr
+from oracle.patch import patch_matrices
+from synthetic_inputs import coefficient_modes, uniform
+
+pytestmark = pytest.mark.gpu
+AMP = 0.1
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def problem(fe, k, n, amp=AMP, seed=2):
+    return fe.Problem(3, k, n, geometry=fe.GEOM_DEFORMED, bc=1, deform_amp=amp, coef=coefficient_modes(seed))
+
+
+def init_params(seed):
+    """Glorot-uniform weights, zero biases (seeded)."""
+    parts = []
+    for i, (no, ni) in enumerate([(64, 64), (64, 64), (12, 64)]):
+        lim = np.sqrt(6.0 / (ni + no))
+        parts += [uniform(no * ni, seed=seed + i, low=-lim, high=lim), np.zeros(no)]
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("k,n", [(2, 3), (3, 4)])
+def test_features_inner_tensor_and_targets(gpu_lib, k, n):
+    fe = gpu_lib
+    m = StructuredMesh(3, k, n)
+    modes, amps, phases = coefficient_modes(2)
+    g = DeformedGeometry(m, AMP, (modes, amps, phases))
+    P = problem(fe, k, n)
+    assert relerr(host(P.patch_features()), patch_features(g, modes, amps, phases)) < 1e-12
+    A = assemble_csr(m, g.element_matrices())
+    E = pieces_1d(k)
+    Pm = patch_matrices(A, m)
+    C = np.array([[np.sum(Pm[p] * np.kron(E[l], np.kron(E[j], E[i])))
+                   for l in range(4) for j in range(4) for i in range(4)] for p in range(Pm.shape[0])])
+    assert relerr(host(P.patch_inner_tensor()), C) < 1e-11
+    t_gpu = host(P.patch_fit_targets(sweeps=10))
+    t_ref = fit_targets(g, A, sweeps=10)
+    assert np.max(np.abs(t_gpu - t_ref)) < 1e-7
+
+
+def test_mlp_forward_gradient_and_adam(gpu_lib):
+    fe = gpu_lib
+    assert fe.MLP_PARAMS == N_PARAMS
+    P = problem(fe, 2, 3)
+    p0 = init_params(10)
+    X = uniform(37 * 64, seed=11).reshape(37, 64)
+    T = uniform(37 * 12, seed=12).reshape(37, 12) * 0.3
+    P.mlp_set_params(torch.as_tensor(p0, dtype=torch.float32, device="cuda"))
+    Xd = torch.as_tensor(X, device="cuda")
+    Td = torch.as_tensor(T, device="cuda")
+    y = host(P.mlp_forward(Xd))
+    assert relerr(y, forward(p0, X)[0]) < 1e-5
+    loss, g = P.mlp_loss_grad(Xd, Td)
+    l_ref, g_ref = loss_and_grad(p0, X, T)
+    assert abs(loss - l_ref) < 1e-5 * l_ref
+    assert relerr(host(g), g_ref) < 1e-4
+    P.mlp_adam_step(g, lr=1e-3)
+    p1, _, _ = adam_step(p0, host(g), np.zeros(N_PARAMS), np.zeros(N_PARAMS), 1, lr=1e-3)
+    assert np.max(np.abs(host(P.mlp_get_params()) - p1)) < 1e-6
+
+
+def test_training_reduces_loss_and_learned_factors_help_pcg(gpu_lib):
+    """Train on patches of generated meshes, then compare PCG iterations: learned vs averaged factors."""
+    fe = gpu_lib
+    k = 2
+    feats, targs = [], []
+    for i, (amp, seed) in enumerate([(0.05, 1000), (0.1, 1001), (0.13, 1002), (0.08, 1003)]):
+        Pt = problem(fe, k, 12, amp=amp, seed=seed)
+        feats.append(Pt.patch_features())
+        targs.append(Pt.patch_fit_targets(sweeps=20))
+        Pt.close()
+    X = torch.cat(feats)
+    T = torch.cat(targs)
+    P = problem(fe, k, 16, amp=AMP, seed=2)
+    P.mlp_set_params(torch.as_tensor(init_params(20), dtype=torch.float32, device="cuda"))
+    l0, _ = P.mlp_loss_grad(X[:4096], T[:4096])
+    loss = P.mlp_train(X, T, epochs=60, batch=256, lr=2e-3, seed=5)
+    assert loss < 0.2 * l0, (l0, loss)
+    b = P.cellvec()
+    P.rhs_manufactured(b)
+    its = {}
+    for factors in (1, 2):
+        x = P.cellvec()
+        opts = fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1, factors=factors,
+                               nu_pre=1, nu_post=1, tol=1e-10)
+        rep = P.pcg_solve(b, x, opts)
+        assert rep["converged"]
+        its[factors] = rep["iters"]
+    assert its[2] <= its[1] + 1, its
