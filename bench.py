@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-deformed", action="store_true")
     ap.add_argument("--only-step", action="store_true", help="time the headline step only (for profilers)")
     ap.add_argument("--with-copy", action="store_true", help="with --only-step: add a plain copy kernel of known size")
     return ap.parse_args()
@@ -100,10 +101,10 @@ def kernel_times(fe, P, sets, reps):
 def kernel_bytes(P, dt_bytes):
     """Algorithmic bytes per launch of each kernel family."""
     k, n = P.degree, P.n
-    m = 2 * k - 1
     n_patches = (n - 1) ** 3
     vec = P.len * dt_bytes
-    wbuf = n_patches * m ** 3 * dt_bytes
+    # patch solutions split by cell slot: 8 blocks of k^3 per patch
+    wbuf = n_patches * 8 * k ** 3 * dt_bytes
     return {"apply": 2 * vec, "fdm_patch": vec + wbuf, "fdm_sum": wbuf + vec}
 
 
@@ -141,6 +142,81 @@ def bench_pcg(fe):
         out[name] = {"seconds": rep["t_solve"], "iters": rep["iters"], "relres": rep["relres"],
                      "setup_s": rep["t_setup"], "converged": rep["converged"], "status": rep["status"]}
         log("pcg %s: %.4f s, %d iters, relres %.2e" % (name, rep["t_solve"], rep["iters"], rep["relres"]))
+    P.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_deformed(fe, k, n, n_train, train_meshes, epochs, with_solve=True):
+    """Deformed, variable-coefficient mesh: general apply rate; MLP trained on generated
+    patches; MG-PCG to 1e-10 with the plain FP64 Jacobi smoother vs FP32 Chebyshev patch-FDM
+    smoothers with averaged and learned factors."""
+    import torch
+    from synthetic_inputs import coefficient_modes, uniform
+    out = {"workload": "Q%d %d^3 deformed (amp 0.1), coefficient exp(smooth field)" % (k, n)}
+    t0 = time.perf_counter()
+    feats, targs = [], []
+    amps = [0.02 + 0.11 * i / max(1, train_meshes - 1) for i in range(train_meshes)]
+    for i, amp in enumerate(amps):
+        Pt = fe.Problem(3, k, n_train, geometry=fe.GEOM_DEFORMED, bc=1, deform_amp=amp,
+                        coef=coefficient_modes(1000 + i))
+        feats.append(Pt.patch_features())
+        targs.append(Pt.patch_fit_targets(sweeps=20))
+        Pt.close()
+    X, T = torch.cat(feats), torch.cat(targs)
+    out["train_patches"] = int(X.shape[0])
+    out["targets_s"] = time.perf_counter() - t0
+    P = fe.Problem(3, k, n, geometry=fe.GEOM_DEFORMED, bc=1, deform_amp=0.1, coef=coefficient_modes(2))
+    out["unique_dofs"] = P.n_dofs
+    # general apply rate
+    for dtype, name in ((torch.float64, "fp64"), (torch.float32, "fp32")):
+        x = torch.as_tensor(uniform(P.len, seed=7), dtype=dtype, device="cuda")
+        y = P.cellvec(dtype)
+        for _ in range(3):
+            P.apply(x, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            P.apply(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        s = 8 if dtype == torch.float64 else 4
+        out["apply_" + name] = {"ms": ms, "gdofs": P.n_dofs / ms / 1e6,
+                                "gbs_algorithmic": (2 * s + 6 * s) * P.len / ms / 1e6}
+        del x, y
+    # model
+    glorot = []
+    for i, (no, ni) in enumerate([(64, 64), (64, 64), (12, 64)]):
+        lim = (6.0 / (ni + no)) ** 0.5
+        glorot += [uniform(no * ni, seed=20 + i, low=-lim, high=lim), [0.0] * no]
+    import numpy as np
+    p0 = torch.as_tensor(np.concatenate([np.asarray(g, dtype=np.float64) for g in glorot]),
+                         dtype=torch.float32, device="cuda")
+    P.mlp_set_params(p0)
+    t1 = time.perf_counter()
+    out["train_final_loss"] = P.mlp_train(X, T, epochs=epochs, batch=256, lr=2e-3, seed=5)
+    out["train_s"] = time.perf_counter() - t1
+    if with_solve:
+        b = P.cellvec()
+        P.rhs_manufactured(b)
+        cases = (("fp64_jacobi_plain", fe.default_opts(smoother=fe.SMOOTH_JACOBI, inner=fe.F64, omega=0.0,
+                                                       nu_pre=2, nu_post=2, tol=1e-10, maxit=400)),
+                 ("fp32_chebfdm_averaged", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
+                                                           factors=1, nu_pre=1, nu_post=1, tol=1e-10)),
+                 ("fp32_chebfdm_learned", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
+                                                          factors=2, nu_pre=1, nu_post=1, tol=1e-10)))
+        for name, opts in cases:
+            x = P.cellvec()
+            P.pcg_solve(b, x, opts, raise_on_error=False)
+            x.zero_()
+            rep = P.pcg_solve(b, x, opts, raise_on_error=False)
+            out[name] = {"seconds": rep["t_solve"], "iters": rep["iters"], "relres": rep["relres"],
+                         "status": rep["status"]}
+            log("deformed Q%d %d^3 %s: %.4f s, %d iters, relres %.2e" % (k, n, name, rep["t_solve"],
+                                                                       rep["iters"], rep["relres"]))
+            del x
     P.close()
     torch.cuda.empty_cache()
     return out
@@ -193,8 +269,6 @@ def main():
     log("Q3 64^3 FP64 step")
     main64 = bench_config(fe, 3, 64, torch.float64, args.steps, args.warmup, nsets=4)
     dom = max(main64["kernel_ms"], key=lambda k: main64["kernel_ms"][k])
-    kb = kernel_bytes(fe.Problem(3, 3, 2, bc=1), 8)  # shapes only
-    P64 = None
     if args.only_step:
         if args.with_copy:
             # calibration for the HBM byte counters: a plain copy of a known size
@@ -202,7 +276,7 @@ def main():
             src = torch.ones(16777216, dtype=torch.float64, device="cuda")
             dst = torch.empty_like(src)
             for _ in range(5):
-                dst.copy_(src)
+                torch.mul(src, 1.5, out=dst)    # elementwise kernel: reads and writes 134,217,728 bytes
             torch.cuda.synchronize()
         print(json.dumps(main64))
         return
@@ -212,6 +286,12 @@ def main():
     q7_64 = bench_config(fe, 7, 32, torch.float64, max(10, args.steps // 2), args.warmup, nsets=4)
     q7_32 = bench_config(fe, 7, 32, torch.float32, max(10, args.steps // 2), args.warmup, nsets=4)
     pcg = None if args.no_pcg else bench_pcg(fe)
+    deformed = {}
+    if not args.no_deformed:
+        log("deformed Q3 48^3 (apply, learned vs averaged factors)")
+        deformed["q3_48cubed"] = bench_deformed(fe, 3, 48, n_train=24, train_meshes=2, epochs=30)
+        log("deformed Q7 64^3 end-to-end solves")
+        deformed["q7_64cubed"] = bench_deformed(fe, 7, 64, n_train=16, train_meshes=6, epochs=30)
     cpu = None if args.no_cpu else cpu_baseline()
 
     # roofline entry for the dominant kernel of the headline step
@@ -238,8 +318,8 @@ def main():
                        "fp32": {"value": round(q7_32["gdofs"], 4), "kernel_ms": q7_32["kernel_ms"]},
                        "unique_dofs": q7_64["n_dofs"]},
         "pcg_q7_32cubed": pcg,
+        "deformed": deformed,
     }
-    del kb, P64
     print(json.dumps(line))
 
 

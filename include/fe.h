@@ -176,7 +176,7 @@ typedef struct {
   int cheb_degree;         /* Chebyshev degree (smoother = 1) */
   double cheb_ratio;       /* interval [lmax/ratio, lmax] */
   double cheb_lmax;        /* > 0: use this lambda_max estimate on every level (tests) */
-  double omega;            /* Jacobi relaxation (smoother = 0) */
+  double omega;            /* Jacobi relaxation (smoother = 0); 0: per level 4/(3 lambda_max(D^-1 A)) */
   int inner;               /* fe_dtype of the V-cycle (FE_F32: FP32 preconditioner) */
   int factors;             /* patch factors for smoother = 1 (see patch_fdm_inverse) */
   int flexible;            /* 1: Polak-Ribiere beta (recommended with inner = FE_F32) */
@@ -212,8 +212,9 @@ fe_status pcg_solve(fe_problem* prob, const void* b_cell, void* x_cell, const fe
 fe_status fe_vcycle(fe_problem* prob, const void* b_cell, void* e_cell, const fe_pcg_opts* opts,
                     fe_dtype dt, void* stream);
 
-/* lambda_max estimate of (patch inverse) * A on `level` by `steps` Lanczos
- * steps (CG coefficients) from a fixed start vector.  Synchronous. */
+/* lambda_max estimate of P A on `level` by `steps` Lanczos steps (CG
+ * coefficients) from a fixed start vector; P = patch inverse (smoother =
+ * FE_SMOOTH_CHEB_FDM) or Jacobi D^{-1} (smoother = FE_SMOOTH_JACOBI).  Synchronous. */
 fe_status fe_estimate_lmax(fe_problem* prob, int level, int smoother, int factors, int steps,
                            double* out, void* stream);
 

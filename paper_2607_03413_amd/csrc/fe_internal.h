@@ -90,6 +90,8 @@ struct Level {
   DeviceBuf fdm_scratch[2];   // patch-major scratch of the patch inverse
   double lmax = 0.0;
   int lmax_key = -1;
+  double omega = 0.7;          // Jacobi damping in use on this level
+  double omega_auto = 0.0;     // cached automatic damping (0: not estimated)
 };
 
 struct Solver;

@@ -18,6 +18,8 @@
 //  (2) one thread per cell-wise entry sums the solutions of the (at most 2^d)
 //      patches containing its node, in a fixed order that depends only on the
 //      node, so every copy receives bit-identical values (continuity).
+#include <type_traits>
+
 #include "fe_internal.h"
 #include "kernel_common.h"
 
@@ -501,6 +503,10 @@ constexpr bool sum_staged_fits() {
   return 4 * (SumTile<K>::TXC + 1) * SumTile<K>::M3 * sizeof(T) <= 64 * 1024;
 }
 
+bool patch_mfma_supported(const fe_problem* p);
+fe_status launch_patch_mfma(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
+                            bool per_patch, double scale, fe_dtype dt, hipStream_t s);
+
 size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt) {
   const Level& L = level_of(p, level);
   const int64_t nv = L.n - 1;
@@ -519,7 +525,9 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
   const int64_t nv = L.n - 1;
   if (p->dim == 3) {
     const int64_t np = nv * nv * nv;
-    if (np > 0) {
+    if (np > 0 && patch_mfma_supported(p)) {
+      FE_CHECK(launch_patch_mfma(p, L, r, W, eig, per_patch, (double)scale, std::is_same<T, double>::value ? FE_F64 : FE_F32, s));
+    } else if (np > 0) {
       constexpr int PPB = PatchLayout<K>::PPB;
       constexpr int THREADS = PatchLayout<K>::THREADS;
       const int segs = (int)((nv + PPB - 1) / PPB);

@@ -34,7 +34,8 @@ struct Solver {
 
 static bool same_setup(const fe_pcg_opts& a, const fe_pcg_opts& b) {
   return a.smoother == b.smoother && a.cheb_degree == b.cheb_degree && a.cheb_ratio == b.cheb_ratio &&
-         a.cheb_lmax == b.cheb_lmax && a.inner == b.inner && a.factors == b.factors && a.precond == b.precond;
+         a.cheb_lmax == b.cheb_lmax && a.inner == b.inner && a.factors == b.factors && a.precond == b.precond &&
+         a.omega == b.omega;
 }
 
 static double* dev_scalar(fe_problem* p, int i) { return p->solver->dscal.as<double>() + i; }
@@ -52,10 +53,19 @@ static fe_status patch_apply(fe_problem* p, int l, const void* r, void* z, fe_dt
   return launch_patch_inverse(p, l, r, z, scr.p, dt, factors, s);
 }
 
-// lambda_max of (patch inverse) A on level l by CG-Lanczos from a fixed start vector.
-static fe_status estimate_lmax(fe_problem* p, int l, int factors, int steps, double* out, hipStream_t s) {
+// lambda_max of P A on level l by CG-Lanczos from a fixed start vector; P is the
+// patch inverse (smoother = FE_SMOOTH_CHEB_FDM) or the Jacobi preconditioner
+// G D^{-1} G^T = S_bar(K_cell D_cell^{-1} .) (smoother = FE_SMOOTH_JACOBI).
+static fe_status estimate_lmax(fe_problem* p, int l, int smoother, int factors, int steps, double* out,
+                               hipStream_t s) {
   Level& L = p->levels[l];
   const int64_t n = L.len;
+  if (smoother == FE_SMOOTH_JACOBI) FE_CHECK(ensure_dinv_level(p, l, s));
+  auto precond = [&](const void* rr, void* zz) -> fe_status {
+    if (smoother == FE_SMOOTH_JACOBI)
+      return launch_jacobi_avg(p, l, rr, rr, rr, L.dinv64.p, zz, 1.0, 1, FE_F64, s);
+    return patch_apply(p, l, rr, zz, FE_F64, factors, s);
+  };
   DeviceBuf x, r, z, pp, q;
   for (DeviceBuf* b : {&x, &r, &z, &pp, &q}) FE_CHECK(b->alloc(n * sizeof(double)));
   // start vector: deterministic hash of the index (counter based), dual
@@ -69,7 +79,7 @@ static fe_status estimate_lmax(fe_problem* p, int l, int factors, int steps, dou
   }
   FE_HIP_CHECK(hipMemcpyAsync(r.p, h.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
   std::vector<double> alpha, beta;
-  FE_CHECK(patch_apply(p, l, r.p, z.p, FE_F64, factors, s));
+  FE_CHECK(precond(r.p, z.p));
   FE_CHECK(launch_cast(n, z.p, FE_F64, pp.p, FE_F64, s));
   FE_CHECK(dot_async(p, n, r.p, z.p, FE_F64, dev_scalar(p, 0), s));
   double rho;
@@ -83,7 +93,7 @@ static fe_status estimate_lmax(fe_problem* p, int l, int factors, int steps, dou
     const double a = rho / pq;
     alpha.push_back(a);
     FE_CHECK(launch_axpby(n, -a, q.p, 1.0, r.p, FE_F64, s));
-    FE_CHECK(patch_apply(p, l, r.p, z.p, FE_F64, factors, s));
+    FE_CHECK(precond(r.p, z.p));
     FE_CHECK(dot_async(p, n, r.p, z.p, FE_F64, dev_scalar(p, 0), s));
     double rho2;
     FE_CHECK(read_scalar(p, 0, &rho2, s));
@@ -125,7 +135,20 @@ fe_status solver_setup(fe_problem* p, const fe_pcg_opts* o, hipStream_t s) {
   for (int l = 0; l < nl; ++l) {
     Level& L = p->levels[l];
     for (DeviceBuf* b : {&L.e[di], &L.b[di], &L.v[di], &L.t[di], &L.w[di]}) FE_CHECK(b->alloc(L.len * es));
-    if (l > 0 && o->smoother == FE_SMOOTH_JACOBI) FE_CHECK(ensure_dinv_level(p, l, s));
+    if (l > 0 && o->smoother == FE_SMOOTH_JACOBI) {
+      FE_CHECK(ensure_dinv_level(p, l, s));
+      if (o->omega != 0.0) {
+        L.omega = o->omega;   // taken literally (a negative value is allowed and diverges)
+      } else if (L.omega_auto <= 0.0) {
+        // automatic damping 4 / (3 lambda_max(D^{-1} A)): 2/3 of the stability limit
+        double lm;
+        FE_CHECK(estimate_lmax(p, l, FE_SMOOTH_JACOBI, 0, 15, &lm, s));
+        L.omega_auto = 4.0 / (3.0 * lm);
+        L.omega = L.omega_auto;
+      } else {
+        L.omega = L.omega_auto;
+      }
+    }
     if (l > 0 && o->smoother == FE_SMOOTH_CHEB_FDM) {
       if (o->factors != 0 && !L.patch_eig_ready[o->factors]) FE_CHECK(setup_patch_factors(p, l, o->factors, s));
       const int key = o->factors * 1000 + 15;
@@ -133,7 +156,7 @@ fe_status solver_setup(fe_problem* p, const fe_pcg_opts* o, hipStream_t s) {
         L.lmax = o->cheb_lmax;
       } else if (L.lmax_key != key) {
         double lm;
-        FE_CHECK(estimate_lmax(p, l, o->factors, 15, &lm, s));
+        FE_CHECK(estimate_lmax(p, l, FE_SMOOTH_CHEB_FDM, o->factors, 15, &lm, s));
         L.lmax = lm;
         L.lmax_key = key;
       }
@@ -155,7 +178,7 @@ static fe_status jacobi_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe
   Level& L = p->levels[l];
   const int di = dt == FE_F64 ? 0 : 1;
   const void* dinv = dt == FE_F64 ? L.dinv64.p : L.dinv32.p;
-  const double omega = p->solver->opts.omega;
+  const double omega = L.omega;
   for (int it = 0; it < sweeps; ++it) {
     const bool z = u_zero && it == 0;
     if (!z) FE_CHECK(launch_apply(p, l, L.e[di].p, L.v[di].p, dt, s));
@@ -312,14 +335,14 @@ fe_status fe_estimate_lmax(fe_problem* p, int level, int smoother, int factors, 
                            void* stream) {
   if (!p || !out) return fail(FE_EINVAL, "null argument");
   FE_CHECK(check_level(p, level));
-  if (smoother != FE_SMOOTH_CHEB_FDM) return fail(FE_EINVAL, "only the patch-preconditioned operator is supported");
+  if (smoother != FE_SMOOTH_CHEB_FDM && smoother != FE_SMOOTH_JACOBI) return fail(FE_EINVAL, "unknown smoother");
   if (steps < 1 || steps > 200) return fail(FE_EINVAL, "steps out of range");
   hipStream_t s = (hipStream_t)stream;
   const int l = level < 0 ? (int)p->levels.size() - 1 : level;
   if (factors != 0 && !p->levels[l].patch_eig_ready[factors]) FE_CHECK(setup_patch_factors(p, l, factors, s));
   if (!p->solver) p->solver = new Solver();
   FE_CHECK(p->solver->dscal.alloc(64 * sizeof(double)));
-  return estimate_lmax(p, l, factors, steps, out, s);
+  return estimate_lmax(p, l, smoother, factors, steps, out, s);
 }
 
 fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o, fe_pcg_report* rep, void* stream) {

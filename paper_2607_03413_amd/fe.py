@@ -241,9 +241,9 @@ class Problem:
         _check(_lib.fe_vcycle(self.h, _ptr(b, self.len, "b"), _ptr(e, self.len, "e"), ctypes.byref(opts), _dt(b),
                               _stream()))
 
-    def estimate_lmax(self, level=-1, factors=0, steps=15):
+    def estimate_lmax(self, level=-1, factors=0, steps=15, smoother=SMOOTH_CHEB_FDM):
         out = ctypes.c_double()
-        _check(_lib.fe_estimate_lmax(self.h, level, SMOOTH_CHEB_FDM, factors, steps, ctypes.byref(out), _stream()))
+        _check(_lib.fe_estimate_lmax(self.h, level, smoother, factors, steps, ctypes.byref(out), _stream()))
         return out.value
 
     # learned per-patch factors

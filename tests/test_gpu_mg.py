@@ -131,6 +131,25 @@ def test_lmax_estimate_brackets_exact(gpu_lib):
     assert 0.9 * exact < est <= exact * (1 + 1e-8), (est, exact)
 
 
+def test_jacobi_lmax_estimate_and_auto_damping(gpu_lib):
+    """lambda_max(D^-1 A) by Lanczos brackets the dense value; omega = 0 selects
+    4 / (3 lambda_max) per level and the resulting PCG converges."""
+    fe = gpu_lib
+    k, n = 3, 4
+    h = Hierarchy(3, k, n)
+    A = h.levels[-1].A.toarray()
+    exact = np.max(np.linalg.eigvalsh(A / np.sqrt(np.outer(np.diag(A), np.diag(A)))))
+    P = fe.Problem(3, k, n, bc=1)
+    est = P.estimate_lmax(-1, steps=15, smoother=fe.SMOOTH_JACOBI)
+    assert 0.9 * exact < est <= exact * (1 + 1e-8), (est, exact)
+    P8 = fe.Problem(3, k, 8, bc=1)
+    b = P8.cellvec()
+    P8.rhs_manufactured(b)
+    x = P8.cellvec()
+    rep = P8.pcg_solve(b, x, fe.default_opts(omega=0.0))
+    assert rep["converged"] and rep["iters"] <= 30
+
+
 @pytest.mark.parametrize("smoother,inner,flexible", [(0, 0, 0), (1, 0, 0), (1, 1, 1), (0, 1, 1)])
 def test_pcg_reaches_exact_discrete_solution(gpu_lib, smoother, inner, flexible):
     fe = gpu_lib
