@@ -90,7 +90,7 @@ def kernel_times(fe, P, sets, reps):
     torch.cuda.synchronize()
     fe.prof_enable(False)
     out = {}
-    for name in ("apply", "fdm_patch", "fdm_sum"):
+    for name in ("apply", "fdm_patch", "fdm_sum", "fdm_fused"):
         c, t = fe.prof_query(name)
         if c:
             out[name] = t / c
@@ -105,7 +105,8 @@ def kernel_bytes(P, dt_bytes):
     vec = P.len * dt_bytes
     # patch solutions split by cell slot: 8 blocks of k^3 per patch
     wbuf = n_patches * 8 * k ** 3 * dt_bytes
-    return {"apply": 2 * vec, "fdm_patch": vec + wbuf, "fdm_sum": wbuf + vec}
+    # the fused patch inverse reads r and writes z once
+    return {"apply": 2 * vec, "fdm_patch": vec + wbuf, "fdm_sum": wbuf + vec, "fdm_fused": 2 * vec}
 
 
 def bench_config(fe, degree, n, dtype, steps, warmup, nsets):

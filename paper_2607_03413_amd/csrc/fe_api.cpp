@@ -223,6 +223,17 @@ fe_status fe_problem_create(const fe_problem_desc* desc, void* stream, fe_proble
     p->co.off_S = put(sl);
     p->co.off_lam = p->co.off_S + M * M;
   }
+  if (p->dim == 3 && k <= 3) {
+    // inverse eigenvalue sums of the Cartesian patch, scaled by h^{2-d} per level
+    std::vector<double> il;
+    for (const Level& L : p->levels) {
+      const double scale = 1.0 / L.h;
+      for (int az = 0; az < M; ++az)
+        for (int ay = 0; ay < M; ++ay)
+          for (int ax = 0; ax < M; ++ax) il.push_back(scale / (p->lam[ax] + p->lam[ay] + p->lam[az]));
+    }
+    p->co.off_il = put(il);
+  }
   std::vector<float> host32(host.begin(), host.end());
   fe_status st = p->coef64.alloc(host.size() * sizeof(double));
   if (st == FE_OK) st = p->coef32.alloc(host32.size() * sizeof(float));

@@ -504,6 +504,8 @@ constexpr bool sum_staged_fits() {
 }
 
 bool patch_mfma_supported(const fe_problem* p);
+bool fused_patch_supported(const fe_problem* p, bool per_patch);
+fe_status launch_patch_fused(const fe_problem* p, int level, const void* r, void* z, fe_dtype dt, hipStream_t s);
 fe_status launch_patch_mfma(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
                             bool per_patch, double scale, fe_dtype dt, hipStream_t s);
 
@@ -566,6 +568,7 @@ fe_status launch_patch_inverse(const fe_problem* p, int level, const void* r, vo
                                fe_dtype dt, int factors, hipStream_t s) {
   const Level& L = level_of(p, level);
   const bool per_patch = factors != 0;
+  if (fused_patch_supported(p, per_patch)) return launch_patch_fused(p, level, r, z, dt, s);
   const double scale = per_patch ? 1.0 : std::pow(L.h, 2 - p->dim);
   const int li = level < 0 ? (int)p->levels.size() - 1 : level;
   const void* eig;
