@@ -19,8 +19,10 @@
 //     (global -> LDS), and the first slices of the next level are fetched
 //     while the current level computes;
 //   * each thread sums the copies of its patch nodes (x pairs, then y, then
-//     z) and applies the six 1D contractions in registers, S and the inverse
-//     eigenvalue sums coming through the scalar cache;
+//     z) and applies the six 1D contractions in registers, using that the
+//     patch eigenvectors are even or odd about the middle node (sums and
+//     differences of mirrored nodes); S and the inverse eigenvalue sums come
+//     through the scalar cache;
 //   * plane by plane, overlaps in x are summed across lanes (lane - 1 holds
 //     patch vx-1) and overlaps in y through LDS (the wave below holds patch
 //     vy-1); the thread that owns cell (vx-1, vy-1, .) holds the merged plane;
@@ -83,24 +85,65 @@ __device__ __forceinline__ T& line_at(T (&w)[M][M][M], int p, int q, int a) {
   return w[a][q][p];
 }
 
-// In-register 1D contraction along axis AX: out_i = sum_a S[a][i] in_a (TRANS)
-// or out_i = sum_a S[i][a] in_a.  S is M x M row-major, uniform across the grid.
-template <int AX, bool TRANS, typename T, int M>
-__device__ __forceinline__ void contract_axis(T (&w)[M][M][M], const T* __restrict__ S) {
+// In-register 1D contraction along axis AX with the mirror-symmetric patch
+// eigenvectors (c = (M-1)/2 is the middle node; modes ordered evens first).
+// Forward (S^T): t_e[j] = sum_{a<c} SE[j][a] (x_a + x_{M-1-a}) + SE[j][c] x_c,
+//                t_o[j] = sum_{a<c} SO[j][a] (x_a - x_{M-1-a}).
+// Backward (S):  E_a = sum_j SE[j][a] t_e[j], O_a = sum_j SO[j][a] t_o[j],
+//                x_a = E_a + O_a, x_{M-1-a} = E_a - O_a, x_c = E_c.
+template <int AX, bool FWD, typename T, int M>
+__device__ __forceinline__ void contract_axis(T (&w)[M][M][M], const T* __restrict__ Seo) {
+  constexpr int c = (M - 1) / 2, ne = c + 1, no = c;
+  const T* __restrict__ SE = Seo;
+  const T* __restrict__ SO = Seo + ne * (c + 1);
 #pragma unroll
   for (int q = 0; q < M; ++q)
 #pragma unroll
     for (int p = 0; p < M; ++p) {
-      T t[M];
+      T x[M], y[M];
 #pragma unroll
-      for (int i = 0; i < M; ++i) {
-        T s = (TRANS ? S[i] : S[i * M]) * line_at<AX>(w, p, q, 0);
+      for (int a = 0; a < M; ++a) x[a] = line_at<AX>(w, p, q, a);
+      if (FWD) {
+        T sum[c + 1], dif[c > 0 ? c : 1];
 #pragma unroll
-        for (int a = 1; a < M; ++a) s = fma(TRANS ? S[a * M + i] : S[i * M + a], line_at<AX>(w, p, q, a), s);
-        t[i] = s;
+        for (int a = 0; a < c; ++a) {
+          sum[a] = x[a] + x[M - 1 - a];
+          dif[a] = x[a] - x[M - 1 - a];
+        }
+        sum[c] = x[c];
+#pragma unroll
+        for (int j = 0; j < ne; ++j) {
+          T s = SE[j * (c + 1)] * sum[0];
+#pragma unroll
+          for (int a = 1; a <= c; ++a) s = fma(SE[j * (c + 1) + a], sum[a], s);
+          y[j] = s;
+        }
+#pragma unroll
+        for (int j = 0; j < no; ++j) {
+          T s = SO[j * c] * dif[0];
+#pragma unroll
+          for (int a = 1; a < c; ++a) s = fma(SO[j * c + a], dif[a], s);
+          y[ne + j] = s;
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a <= c; ++a) {
+          T e = SE[a] * x[0];
+#pragma unroll
+          for (int j = 1; j < ne; ++j) e = fma(SE[j * (c + 1) + a], x[j], e);
+          if (a == c) {
+            y[c] = e;
+          } else {
+            T o = SO[a] * x[ne];
+#pragma unroll
+            for (int j = 1; j < no; ++j) o = fma(SO[j * c + a], x[ne + j], o);
+            y[a] = e + o;
+            y[M - 1 - a] = e - o;
+          }
+        }
       }
 #pragma unroll
-      for (int i = 0; i < M; ++i) line_at<AX>(w, p, q, i) = t[i];
+      for (int a = 0; a < M; ++a) line_at<AX>(w, p, q, a) = y[a];
     }
 }
 
@@ -210,8 +253,8 @@ __device__ __forceinline__ void pull_slice(T (&w)[M][M][M], lds_ptr<T> lb, int s
 }
 
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z,
-                                                    const T* __restrict__ S, const T* __restrict__ il, int n,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
+k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ Seo, const T* __restrict__ il, int n,
                                                     int nxt, int nyt, int zlen) {
   using FP = FusedPatch<T, K>;
   constexpr int k = FP::k, M = FP::M, WY = FP::WY, K2 = FP::K2, K3 = K2 * K;
@@ -291,18 +334,18 @@ __global__ void __launch_bounds__(256) k_fdm_fused3(const T* __restrict__ r, T* 
         for (int s = 0; s < NBUF; ++s) stage_slice<T, K>(sbuf + s * SLICE, r, s, vz + 1, X0, Y0, n, tid);
       }
       // (2) fast diagonalization in registers
-      contract_axis<2, true>(w, S);
-      contract_axis<1, true>(w, S);
-      contract_axis<0, true>(w, S);
+      contract_axis<2, true>(w, Seo);
+      contract_axis<1, true>(w, Seo);
+      contract_axis<0, true>(w, Seo);
 #pragma unroll
       for (int az = 0; az < M; ++az)
 #pragma unroll
         for (int ay = 0; ay < M; ++ay)
 #pragma unroll
           for (int ax = 0; ax < M; ++ax) w[az][ay][ax] *= il[(az * M + ay) * M + ax];
-      contract_axis<0, false>(w, S);
-      contract_axis<1, false>(w, S);
-      contract_axis<2, false>(w, S);
+      contract_axis<0, false>(w, Seo);
+      contract_axis<1, false>(w, Seo);
+      contract_axis<2, false>(w, Seo);
     } else {
 #pragma unroll
       for (int az = 0; az < M; ++az)
@@ -398,7 +441,7 @@ __global__ void __launch_bounds__(256) k_fdm_fused3(const T* __restrict__ r, T* 
 }
 
 bool fused_patch_supported(const fe_problem* p, bool per_patch) {
-  return p->dim == 3 && !per_patch && p->k >= 2 && p->k <= 3 && p->co.off_il >= 0;
+  return p->dim == 3 && !per_patch && p->k >= 2 && p->k <= 3 && p->co.off_il >= 0 && p->co.off_Seo >= 0;
 }
 
 // Number of x-tiles: tile t owns cells up to X0 + 61 = 62 (t + 1), or up to
@@ -437,10 +480,10 @@ static fe_status fused_typed(const fe_problem* p, int li, const T* r, T* z, cons
   }
   const int nzc = (n + best_len - 1) / best_len;
   const int64_t blocks = (int64_t)nxt * nyt * nzc;
-  const T* S = coef + p->co.off_S;
+  const T* Seo = coef + p->co.off_Seo;
   const T* il = coef + p->co.off_il + (int64_t)li * M * M * M;
   ProfScope ps("fdm_fused", s);
-  hipLaunchKernelGGL((k_fdm_fused3<T, K>), dim3((unsigned)blocks), dim3(256), 0, s, r, z, S, il, n, nxt, nyt,
+  hipLaunchKernelGGL((k_fdm_fused3<T, K>), dim3((unsigned)blocks), dim3(256), 0, s, r, z, Seo, il, n, nxt, nyt,
                      best_len);
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
