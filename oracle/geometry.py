@@ -29,10 +29,13 @@ def deform(xh, amp):
     return xh + amp * s[..., None]
 
 
-def cell_node_coords(mesh, amp):
-    """(n_cells, K^3, 3) physical coordinates of every cell's Q_k geometry nodes."""
+def cell_node_coords(mesh, amp, cells=None):
+    """(n_cells, K^3, 3) physical coordinates of the cells' Q_k geometry nodes
+    (all cells, or the listed cell indices)."""
     xi = gll_nodes(mesh.k)
     cc = mesh.cell_coords()
+    if cells is not None:
+        cc = cc[np.asarray(cells)]
     lc = mesh.local_coords()
     ref = (cc[:, None, :] + xi[lc][None, :, :]) / mesh.n
     return deform(ref, amp)
@@ -66,16 +69,41 @@ def coefficient_raw(x, modes, amps, phases):
     return np.cos(arg) @ amps
 
 
-class DeformedGeometry:
-    """Quadrature data of the deformed, variable-coefficient problem on one structured mesh."""
+def coefficient_scale(mesh, amp, coef, chunk=2048):
+    """s = 1 / max |sum_j a_j cos(pi m_j . x_q + phi_j)| over the (k+1)^3 Gauss
+    points x_q of every cell of `mesh`, evaluated chunk by chunk of cells."""
+    from concurrent.futures import ThreadPoolExecutor
+    modes, amps, phases = (np.asarray(c) for c in coef)
+    k = mesh.k
+    xq, _ = gauss_legendre(k + 1)
+    V, _ = tensor_basis(k, xq)
 
-    def __init__(self, mesh, amp, coef, scale=None):
+    def chunk_max(c0):
+        X = cell_node_coords(mesh, amp, cells=np.arange(c0, min(mesh.n_cells, c0 + chunk)))
+        xphys = np.einsum("qj,ejd->eqd", V, X)
+        return float(np.max(np.abs(coefficient_raw(xphys, modes, amps, phases))))
+
+    # chunks are independent; the maximum does not depend on their order
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        gmax = max(ex.map(chunk_max, range(0, mesh.n_cells, chunk)))
+    return 1.0 / gmax
+
+
+class DeformedGeometry:
+    """Quadrature data of the deformed, variable-coefficient problem on one structured mesh
+    (all cells, or the listed cell indices; the coefficient scale s is then taken from
+    `scale`, which a caller computes over the whole mesh with coefficient_scale)."""
+
+    def __init__(self, mesh, amp, coef, scale=None, cells=None):
         self.mesh, self.amp = mesh, amp
+        self.cells = None if cells is None else np.asarray(cells)
+        if self.cells is not None and scale is None and coef is not None and len(coef[1]):
+            raise ValueError("a cell subset needs the whole-mesh coefficient scale")
         k = mesh.k
         self.xq, self.wq = gauss_legendre(k + 1)
         self.V, self.Gr = tensor_basis(k, self.xq)
         self.W = tensor_weights(self.wq)
-        X = cell_node_coords(mesh, amp)                            # (E, K^3, 3)
+        X = cell_node_coords(mesh, amp, cells=self.cells)           # (E, K^3, 3)
         self.X = X
         self.xphys = np.einsum("qj,ejd->eqd", self.V, X)           # (E, Q, 3)
         # J[e, q, d, a] = d x_d / d xi_a
@@ -100,7 +128,7 @@ class DeformedGeometry:
 
     def apply(self, x_cell):
         """y_K = A_K x_K via the quadrature definition (gradients, metric, integrate)."""
-        x = np.asarray(x_cell).reshape(self.mesh.n_cells, -1)
+        x = np.asarray(x_cell).reshape(self.G.shape[0], -1)
         grad = np.einsum("qja,ej->eqa", self.Gr, x)
         flux = np.einsum("eqab,eqb->eqa", self.G, grad)
         return np.einsum("qia,eqa->ei", self.Gr, flux)

@@ -50,13 +50,12 @@ class StructuredMesh:
 
     def global_index_map(self):
         """(n_cells, K^d) array: global DoF index of every cell-wise entry."""
+        # global coordinate k*c + i per axis, flattened x fastest:
+        # sum_a N^a (k c_a + i_a) = (sum_a N^a k c_a) + (sum_a N^a i_a)
         cc = self.cell_coords()
         lc = self.local_coords()
-        g = self.k * cc[:, None, :] + lc[None, :, :]
-        idx = g[..., 0] + self.N * g[..., 1]
-        if self.dim == 3:
-            idx = idx + self.N * self.N * g[..., 2]
-        return idx
+        stride = self.N ** np.arange(self.dim)
+        return (self.k * cc @ stride)[:, None] + (lc @ stride)[None, :]
 
     def global_coords(self):
         """(n_global, dim) integer node coordinates of every global DoF."""
@@ -86,9 +85,8 @@ class StructuredMesh:
 
     def assemble(self, y_cell):
         """G^T y: sum cell-wise copies into global DoFs."""
-        out = np.zeros(self.n_global, dtype=np.result_type(y_cell, np.float64))
-        np.add.at(out, self.global_index_map().ravel(), np.asarray(y_cell).ravel())
-        return out
+        y = np.asarray(y_cell, dtype=np.result_type(y_cell, np.float64)).ravel()
+        return np.bincount(self.global_index_map().ravel(), weights=y, minlength=self.n_global)
 
     def valence_global(self):
         """kappa = diag(G^T G): number of cells sharing each global DoF."""

@@ -101,3 +101,21 @@ def test_averaged_separable_fit_tracks_deformed_patch():
     P = patch_matrices(A, m)
     rel = [np.linalg.norm(sep_matrix(2, w[p]) - P[p]) / np.linalg.norm(P[p]) for p in range(P.shape[0])]
     assert 1e-3 < max(rel) < 0.6
+
+
+def test_chunked_scale_and_cell_subset_match_whole_mesh():
+    """The chunked coefficient scale equals the whole-mesh one, and the geometry of
+    a cell subset (given that scale) equals the whole-mesh geometry on those cells."""
+    from oracle.geometry import coefficient_scale
+    m = StructuredMesh(3, 2, 3)
+    coef = coefficient_modes(5)
+    full = DeformedGeometry(m, 0.1, coef)
+    assert coefficient_scale(m, 0.1, coef, chunk=4) == full.scale
+    cells = np.array([0, 5, 13, 26])
+    sub = DeformedGeometry(m, 0.1, coef, scale=full.scale, cells=cells)
+    assert np.array_equal(sub.element_matrices(), full.element_matrices()[cells])
+    x = uniform(len(cells) * m.n_local, seed=4).reshape(len(cells), -1)
+    ref = np.einsum("eij,ej->ei", full.element_matrices()[cells], x)
+    assert np.max(np.abs(sub.apply(x) - ref)) < 1e-12 * np.abs(ref).max()
+    with pytest.raises(ValueError):
+        DeformedGeometry(m, 0.1, coef, cells=cells)
