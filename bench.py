@@ -98,6 +98,29 @@ def kernel_times(fe, P, sets, reps):
     return out
 
 
+def measured_traffic(family):
+    """HBM bytes per launch of a kernel family from the committed counter summaries
+    under profiles/ (FETCH_SIZE and WRITE_SIZE passes, calibrated on a plain copy),
+    or None when none was taken on the kernel source as it is now."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            t = line.split()
+            if not t or t[0] != "traffic":
+                continue
+            kv = dict(x.split("=", 1) for x in t[1:] if "=" in x)
+            if kv.get("family") != family:
+                continue
+            src = os.path.join(ROOT, kv.get("source", ""))
+            if not os.path.isfile(src):
+                continue
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("sha256"):
+                continue
+            return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def kernel_bytes(P, dt_bytes):
     """Algorithmic bytes per launch of each kernel family."""
     k, n = P.degree, P.n
@@ -302,7 +325,7 @@ def main():
     P.close()
     achieved = bytes_dom / (k_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
             "avg_launch_ms": round(k_ms, 5), "algorithmic_bytes": bytes_dom}
     line = {
         "metric": METRIC, "value": round(main64["gdofs"], 4), "unit": "GDoF/s", "n_gpus": 1,
