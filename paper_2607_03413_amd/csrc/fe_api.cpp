@@ -223,12 +223,13 @@ fe_status fe_problem_create(const fe_problem_desc* desc, void* stream, fe_proble
     p->co.off_S = put(sl);
     p->co.off_lam = p->co.off_S + M * M;
   }
-  if (p->dim == 3 && k >= 2 && k <= 3) {
+  if (p->dim == 3 && k >= 2) {
     // The two-cell patch is mirror symmetric, so every 1D eigenvector is even
     // or odd about the middle node c = k-1.  Modes are reordered evens first;
     // SE[je][a] (a = 0..c) and SO[jo][a] (a = 0..c-1) hold the left half of
-    // the even and odd eigenvectors, which the fused kernel applies to sums and
-    // differences of mirrored nodes.
+    // the even and odd eigenvectors, followed by the M eigenvalues in that
+    // order.  The patch kernels apply them to sums and differences of
+    // mirrored nodes.
     const int c = k - 1, ne = c + 1, no = c;
     std::vector<int> even, odd;
     for (int j = 0; j < M; ++j) {
@@ -237,24 +238,26 @@ fe_status fe_problem_create(const fe_problem_desc* desc, void* stream, fe_proble
       (sym > 0.0 ? even : odd).push_back(j);
     }
     if ((int)even.size() == ne && (int)odd.size() == no) {
-      std::vector<double> seo;
+      std::vector<double> seo, lm(M);
       for (int je = 0; je < ne; ++je)
         for (int a = 0; a <= c; ++a) seo.push_back(p->S[a * M + even[je]]);
       for (int jo = 0; jo < no; ++jo)
         for (int a = 0; a < c; ++a) seo.push_back(p->S[a * M + odd[jo]]);
-      p->co.off_Seo = put(seo);
-      std::vector<double> lm(M);
       for (int je = 0; je < ne; ++je) lm[je] = p->lam[even[je]];
       for (int jo = 0; jo < no; ++jo) lm[ne + jo] = p->lam[odd[jo]];
-      // inverse eigenvalue sums in that mode order, scaled by h^{2-d} per level
-      std::vector<double> il;
-      for (const Level& L : p->levels) {
-        const double scale = 1.0 / L.h;
-        for (int mz = 0; mz < M; ++mz)
-          for (int my = 0; my < M; ++my)
-            for (int mx = 0; mx < M; ++mx) il.push_back(scale / (lm[mx] + lm[my] + lm[mz]));
+      seo.insert(seo.end(), lm.begin(), lm.end());
+      p->co.off_Seo = put(seo);
+      if (k <= 3) {
+        // inverse eigenvalue sums in that mode order, scaled by h^{2-d} per level
+        std::vector<double> il;
+        for (const Level& L : p->levels) {
+          const double scale = 1.0 / L.h;
+          for (int mz = 0; mz < M; ++mz)
+            for (int my = 0; my < M; ++my)
+              for (int mx = 0; mx < M; ++mx) il.push_back(scale / (lm[mx] + lm[my] + lm[mz]));
+        }
+        p->co.off_il = put(il);
       }
-      p->co.off_il = put(il);
     }
   }
   std::vector<float> host32(host.begin(), host.end());

@@ -505,6 +505,9 @@ constexpr bool sum_staged_fits() {
 
 bool patch_mfma_supported(const fe_problem* p);
 bool fused_patch_supported(const fe_problem* p, bool per_patch);
+bool patch_wave_supported(const fe_problem* p, bool per_patch);
+fe_status launch_patch_wave(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
+                            bool per_patch, double scale, fe_dtype dt, hipStream_t s);
 fe_status launch_patch_fused(const fe_problem* p, int level, const void* r, void* z, fe_dtype dt, hipStream_t s);
 fe_status launch_patch_mfma(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
                             bool per_patch, double scale, fe_dtype dt, hipStream_t s);
@@ -527,7 +530,9 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
   const int64_t nv = L.n - 1;
   if (p->dim == 3) {
     const int64_t np = nv * nv * nv;
-    if (np > 0 && patch_mfma_supported(p)) {
+    if (np > 0 && patch_wave_supported(p, per_patch)) {
+      FE_CHECK(launch_patch_wave(p, L, r, W, eig, per_patch, (double)scale, std::is_same<T, double>::value ? FE_F64 : FE_F32, s));
+    } else if (np > 0 && patch_mfma_supported(p)) {
       FE_CHECK(launch_patch_mfma(p, L, r, W, eig, per_patch, (double)scale, std::is_same<T, double>::value ? FE_F64 : FE_F32, s));
     } else if (np > 0) {
       constexpr int PPB = PatchLayout<K>::PPB;

@@ -76,31 +76,55 @@ __device__ __forceinline__ int dest_index(int a2, int q) {
 }
 
 // One contraction: out = Amat * in, Amat given as 4 register chunks (lane l holds
-// Amat[l % 16][4 c + l / 16] in a[c]).  Optional eigenvalue division (MODE
-// TO_LX_SAME): out[x'][y + M z] *= scale / (lx[x'] + ly[y] + lz[z]).
+// Amat[l % 16][4 c + l / 16] in a[c]).  The wavefront's tiles (t = wave, wave + 4,
+// ...) are issued back to back so that their MFMA chains overlap.  Optional
+// eigenvalue scaling (MODE TO_LX_SAME): out[x'][y + M z] *= inv[x' + M (y + M z)].
 template <typename T, int M, int RP, int TILES, int MODE>
 __device__ __forceinline__ void contract(const T* __restrict__ in, T* __restrict__ out, const T (&a)[4], int wave,
-                                         int lane, const T* lx, const T* ly, const T* lz, T scale) {
+                                         int lane, const T* __restrict__ inv) {
   typedef typename Mfma<T>::acc acc;
   constexpr int R = M * M;
+  constexpr int TPW = (TILES + 3) / 4;   // tiles per wavefront (at most)
   const int j = lane & 15, kk = lane >> 4;
-  for (int t = wave; t < TILES; t += 4) {
-    acc d = {0, 0, 0, 0};
-    const int col = 16 * t + j;
+  acc d[TPW];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) d = Mfma<T>::step(a[c], in[(4 * c + kk) * RP + col], d);
-    if (col < R) {
+  for (int i = 0; i < TPW; ++i) d[i] = acc{0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = wave + 4 * i;
+      if (t < TILES) d[i] = Mfma<T>::step(a[c], in[(4 * c + kk) * RP + 16 * t + j], d[i]);
+    }
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int col = 16 * (wave + 4 * i) + j;
+    if (wave + 4 * i < TILES && col < R) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a2 = Mfma<T>::row(lane, r);
         if (a2 < M) {
-          T v = d[r];
-          if (MODE == TO_LX_SAME) v = v * scale / (lx[a2] + ly[col % M] + lz[col / M]);
+          T v = d[i][r];
+          if (MODE == TO_LX_SAME) v *= inv[a2 + M * col];
           out[dest_index<M, RP, MODE>(a2, col)] = v;
         }
       }
     }
   }
+}
+
+// Copies of patch-local node a (0 <= a <= 2k-2) along one axis: cell slot
+// (0 = lower cell, 1 = upper cell) and local index, lower slot first.
+template <int K>
+__device__ __forceinline__ AxisCopies mfma_axis_copies(int a) {
+  constexpr int k = K - 1;
+  AxisCopies c;
+  const int o = a + 1;
+  if (o < k) { c.cnt = 1; c.c[0] = 0; c.i[0] = o; }
+  else if (o > k) { c.cnt = 1; c.c[0] = 1; c.i[0] = o - k; }
+  else { c.cnt = 2; c.c[0] = 0; c.i[0] = k; c.c[1] = 1; c.i[1] = 0; }
+  if (c.cnt == 1) { c.c[1] = c.c[0]; c.i[1] = c.i[0]; }
+  return c;
 }
 
 template <typename T, int K, bool PER_PATCH>
@@ -110,10 +134,11 @@ __global__ void __launch_bounds__(256) k_fdm_patch3_mfma(const T* __restrict__ r
   constexpr int k = P::k, M = P::M, RP = P::RP, TS = P::TS, TILES = P::TILES, K3 = P::K3;
   constexpr int CELLS = 8 * K3;
   constexpr int BUF0 = CELLS > TS ? CELLS : TS;
-  __shared__ T lds[BUF0 + TS];
-  __shared__ T lam[3 * 16];
-  T* b0 = lds;          // staged cells, then tensor buffer 0
-  T* b1 = lds + BUF0;   // tensor buffer 1
+  constexpr int M3 = M * M * M;
+  __shared__ T lds[BUF0 + TS + M3];
+  T* b0 = lds;              // staged cells, then tensor buffer 0
+  T* b1 = lds + BUF0;       // tensor buffer 1
+  T* inv = b1 + TS;         // scale / (lx + ly + lz), index x + M (y + M z)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nv = n - 1;
   const int64_t pid = blockIdx.x;
@@ -131,44 +156,50 @@ __global__ void __launch_bounds__(256) k_fdm_patch3_mfma(const T* __restrict__ r
     Sx = Sy = Sz = eig;
     lsrc[0] = lsrc[1] = lsrc[2] = eig + M * M;
   }
-  if (tid < 48) {
-    const int d = tid / 16, i = tid % 16;
-    lam[tid] = i < M ? lsrc[d][i] : T(1);
-  }
   // stage the 8 cells of the patch: slot s = sx + 2 sy + 4 sz, contiguous K^3 each
-  for (int e = tid; e < CELLS; e += 256) {
-    const int s = e / K3, loc = e - s * K3;
-    const int64_t cell = (vx - 1 + (s & 1)) + (int64_t)n * ((vy - 1 + ((s >> 1) & 1)) + (int64_t)n * (vz - 1 + (s >> 2)));
-    b0[e] = r[cell * K3 + loc];
+  {
+    const int64_t c0 = (vx - 1) + (int64_t)n * ((vy - 1) + (int64_t)n * (vz - 1));
+    const int64_t sy = n, sz = (int64_t)n * n;
+#pragma unroll 4
+    for (int e = tid; e < CELLS; e += 256) {
+      const int s = e / K3, loc = e - s * K3;
+      const int64_t cell = c0 + (s & 1) + sy * ((s >> 1) & 1) + sz * (s >> 2);
+      b0[e] = r[cell * K3 + loc];
+    }
+  }
+  // inverse eigenvalue sums
+  for (int e = tid; e < M3; e += 256) {
+    const int x = e % M, y = (e / M) % M, z = e / (M * M);
+    inv[e] = scale / (lsrc[0][x] + lsrc[1][y] + lsrc[2][z]);
   }
   // zero the padding rows M..15 of buffer 1 (buffer 0's are zeroed after the gather)
   for (int e = tid; e < (16 - M) * RP; e += 256) b1[M * RP + e] = T(0);
   __syncthreads();
-  // assemble the patch residual (cascade order) into LZ of buffer 1
-  for (int node = tid; node < M * M * M; node += 256) {
-    const int x = node % M, y = (node / M) % M, z = node / (M * M);
-    const int o[3] = {x + 1, y + 1, z + 1};
-    int cnt[3], sl[3][2], il[3][2];
-    for (int a = 0; a < 3; ++a) {
-      if (o[a] < k) { cnt[a] = 1; sl[a][0] = 0; il[a][0] = o[a]; }
-      else if (o[a] > k) { cnt[a] = 1; sl[a][0] = 1; il[a][0] = o[a] - k; }
-      else { cnt[a] = 2; sl[a][0] = 0; il[a][0] = k; sl[a][1] = 1; il[a][1] = 0; }
-    }
-    T zs[2];
-    for (int sz = 0; sz < cnt[2]; ++sz) {
-      T ys[2];
-      for (int sy = 0; sy < cnt[1]; ++sy) {
-        T xs = T(0);
-        for (int sx = 0; sx < cnt[0]; ++sx) {
-          const int s = sl[0][sx] + 2 * sl[1][sy] + 4 * sl[2][sz];
-          const T v = b0[s * K3 + il[0][sx] + K * (il[1][sy] + K * il[2][sz])];
-          xs = sx ? xs + v : v;
+  // assemble the patch residual into LZ of buffer 1: thread = (x, y) pencil,
+  // copies summed in cascade order (x pairs, then y, then z)
+  if (tid < M * M) {
+    const int x = tid % M, y = tid / M;
+    const AxisCopies cx = mfma_axis_copies<K>(x), cy = mfma_axis_copies<K>(y);
+#pragma unroll
+    for (int z = 0; z < M; ++z) {
+      const AxisCopies cz = mfma_axis_copies<K>(z);
+      T zs = T(0);
+#pragma unroll
+      for (int sz = 0; sz < 2; ++sz) {
+        if (sz >= cz.cnt) break;
+        T ys = T(0);
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy) {
+          if (sy >= cy.cnt) break;
+          const T* cb = b0 + (4 * cz.c[sz] + 2 * cy.c[sy]) * K3 + K * (cy.i[sy] + K * cz.i[sz]);
+          T xs = cb[cx.c[0] * K3 + cx.i[0]];
+          if (cx.cnt == 2) xs += cb[cx.c[1] * K3 + cx.i[1]];
+          ys = sy == 0 ? xs : ys + xs;
         }
-        ys[sy] = xs;
+        zs = sz == 0 ? ys : zs + ys;
       }
-      zs[sz] = cnt[1] == 2 ? ys[0] + ys[1] : ys[0];
+      b1[z * RP + x + M * y] = zs;
     }
-    b1[z * RP + x + M * y] = cnt[2] == 2 ? zs[0] + zs[1] : zs[0];
   }
   __syncthreads();
   for (int e = tid; e < (16 - M) * RP; e += 256) b0[M * RP + e] = T(0);
@@ -189,31 +220,45 @@ __global__ void __launch_bounds__(256) k_fdm_patch3_mfma(const T* __restrict__ r
     }
   }
   __syncthreads();
-  const T* lx = lam;
-  const T* ly = lam + 16;
-  const T* lz = lam + 32;
-  contract<T, M, RP, TILES, TO_LY_FROM_LZ>(b1, b0, fz, wave, lane, lx, ly, lz, scale);
+  contract<T, M, RP, TILES, TO_LY_FROM_LZ>(b1, b0, fz, wave, lane, inv);
   __syncthreads();
-  contract<T, M, RP, TILES, TO_LX_FROM_LY>(b0, b1, fy, wave, lane, lx, ly, lz, scale);
+  contract<T, M, RP, TILES, TO_LX_FROM_LY>(b0, b1, fy, wave, lane, inv);
   __syncthreads();
-  contract<T, M, RP, TILES, TO_LX_SAME>(b1, b0, fx, wave, lane, lx, ly, lz, scale);
+  contract<T, M, RP, TILES, TO_LX_SAME>(b1, b0, fx, wave, lane, inv);
   __syncthreads();
-  contract<T, M, RP, TILES, TO_LY_FROM_LX>(b0, b1, gx, wave, lane, lx, ly, lz, scale);
+  contract<T, M, RP, TILES, TO_LY_FROM_LX>(b0, b1, gx, wave, lane, inv);
   __syncthreads();
-  contract<T, M, RP, TILES, TO_LZ_FROM_LY>(b1, b0, gy, wave, lane, lx, ly, lz, scale);
+  contract<T, M, RP, TILES, TO_LZ_FROM_LY>(b1, b0, gy, wave, lane, inv);
   __syncthreads();
-  contract<T, M, RP, TILES, TO_LZ_SAME>(b0, b1, gz, wave, lane, lx, ly, lz, scale);
+  contract<T, M, RP, TILES, TO_LZ_SAME>(b0, b1, gz, wave, lane, inv);
   __syncthreads();
-  // slot-split output (8 k^3 contiguous values per patch), read from LZ of buffer 1
+  // slot-split output (8 k^3 contiguous values per patch) from LZ of buffer 1:
+  // thread = (x, y) pencil; node a of an axis lies in slot 0 at a (a <= k-1) and
+  // in slot 1 at a - (k-1) (a >= k-1)
   constexpr int k3 = k * k * k;
   T* wp = W + pid * (8 * k3);
-  for (int e = tid; e < 8 * k3; e += 256) {
-    const int s = e / k3, q = e - s * k3;
-    const int jx = q % k, jy = (q / k) % k, jz = q / (k * k);
-    const int x = (s & 1) ? jx + k - 1 : jx;
-    const int y = ((s >> 1) & 1) ? jy + k - 1 : jy;
-    const int z = (s >> 2) ? jz + k - 1 : jz;
-    wp[e] = b1[z * RP + x + M * y];
+  if (tid < M * M) {
+    const int x = tid % M, y = tid / M;
+#pragma unroll
+    for (int z = 0; z < M; ++z) {
+      const T v = b1[z * RP + x + M * y];
+#pragma unroll
+      for (int szs = 0; szs < 2; ++szs) {
+        const int jz = szs ? z - (k - 1) : z;
+        if (jz < 0 || jz >= k) continue;
+#pragma unroll
+        for (int sys = 0; sys < 2; ++sys) {
+          const int jy = sys ? y - (k - 1) : y;
+          if (jy < 0 || jy >= k) continue;
+#pragma unroll
+          for (int sxs = 0; sxs < 2; ++sxs) {
+            const int jx = sxs ? x - (k - 1) : x;
+            if (jx < 0 || jx >= k) continue;
+            wp[(sxs + 2 * sys + 4 * szs) * k3 + jx + k * (jy + k * jz)] = v;
+          }
+        }
+      }
+    }
   }
 }
 

@@ -1,0 +1,316 @@
+// Vertex-patch fast-diagonalization inverse with one wavefront per patch
+// (3D, k >= 4: m = 2k-1 = 7..15, m^3 patch values in LDS).
+//
+// z = G sum_p R_p^T (S_x x S_y x S_z) (L_x + L_y + L_z)^{-1} (S_x x S_y x S_z)^T R_p G^T r
+// (vertex-patch smoother admissible by eq. precond_consistency, Sec. 2.1;
+// fast diagonalization of the separable patch operator).  The 1D factors
+// are uniform over a wavefront, so S and the eigenvalues are read through
+// the scalar cache and every FMA takes one operand from a scalar register:
+//   * lanes own pencils (lines of m values) of the patch, lane + 64 i;
+//   * the residual is assembled per z-pencil straight from the cell-wise
+//     input (copies summed in cascade order: x pairs, then y, then z) and
+//     contracted with S_z^T in registers before it reaches LDS;
+//   * y: S_y^T; x: S_x^T, scaling by the inverse eigenvalue sums, S_x; y: S_y,
+//     each an in-place pass over LDS lines (no two lanes share a line, so a
+//     wavefront-level fence between the passes suffices);
+//   * z: S_z in registers, and the result is written slot by slot (the k^3
+//     patch nodes inside each of the 8 cells) for the slot-sum pass.
+// With the exact Cartesian factors the mirror symmetry of the two-cell patch
+// is used: every eigenvector is even or odd about the middle node, so a
+// line costs (c+1)^2 + c^2 instead of m^2 FMAs (c = k-1).
+#include "fe_internal.h"
+#include "kernel_common.h"
+
+namespace fe {
+
+template <int K>
+struct WavePatch {
+  static constexpr int k = K - 1;
+  static constexpr int M = 2 * k - 1;
+  static constexpr int M2 = M * M;
+  static constexpr int M3 = M2 * M;
+  static constexpr int ROUNDS = (M2 + 63) / 64;
+  static constexpr int C = k - 1;         // middle node
+  static constexpr int NE = C + 1, NO = C;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1 / x: hardware reciprocal refined by Newton steps r <- r (2 - x r).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  r = r * fma(-x, r, 2.0);
+  return r;
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return r * fmaf(-x, r, 2.0f);
+}
+
+// y = S^T x (FWD) or y = S x for one line.  EO: S given by its even/odd
+// halves (modes ordered evens first); otherwise S is M x M row-major, S[a*M + j].
+template <typename T, int M, bool EO, bool FWD>
+__device__ __forceinline__ void line_apply(const T* __restrict__ S, const T (&x)[M], T (&y)[M]) {
+  if (EO) {
+    constexpr int c = (M - 1) / 2, ne = c + 1, no = c;
+    const T* __restrict__ SE = S;
+    const T* __restrict__ SO = S + ne * (c + 1);
+    if (FWD) {
+      T sum[c + 1], dif[c > 0 ? c : 1];
+#pragma unroll
+      for (int a = 0; a < c; ++a) {
+        sum[a] = x[a] + x[M - 1 - a];
+        dif[a] = x[a] - x[M - 1 - a];
+      }
+      sum[c] = x[c];
+#pragma unroll
+      for (int j = 0; j < ne; ++j) {
+        T s = SE[j * (c + 1)] * sum[0];
+#pragma unroll
+        for (int a = 1; a <= c; ++a) s = fma(SE[j * (c + 1) + a], sum[a], s);
+        y[j] = s;
+      }
+#pragma unroll
+      for (int j = 0; j < no; ++j) {
+        T s = SO[j * c] * dif[0];
+#pragma unroll
+        for (int a = 1; a < c; ++a) s = fma(SO[j * c + a], dif[a], s);
+        y[ne + j] = s;
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a <= c; ++a) {
+        T e = SE[a] * x[0];
+#pragma unroll
+        for (int j = 1; j < ne; ++j) e = fma(SE[j * (c + 1) + a], x[j], e);
+        if (a == c) {
+          y[c] = e;
+        } else {
+          T o = SO[a] * x[ne];
+#pragma unroll
+          for (int j = 1; j < no; ++j) o = fma(SO[j * c + a], x[ne + j], o);
+          y[a] = e + o;
+          y[M - 1 - a] = e - o;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      T s = (FWD ? S[i] : S[i * M]) * x[0];
+#pragma unroll
+      for (int a = 1; a < M; ++a) s = fma(FWD ? S[a * M + i] : S[i * M + a], x[a], s);
+      y[i] = s;
+    }
+  }
+}
+
+// Copies of patch-local node a (0 <= a <= 2k-2) along one axis: cell slot
+// (0 = lower cell, 1 = upper cell) and local index, lower slot first.
+template <int K>
+__device__ __forceinline__ AxisCopies wave_axis_copies(int a) {
+  constexpr int k = K - 1;
+  AxisCopies c;
+  const int o = a + 1;
+  if (o < k) { c.cnt = 1; c.c[0] = 0; c.i[0] = o; }
+  else if (o > k) { c.cnt = 1; c.c[0] = 1; c.i[0] = o - k; }
+  else { c.cnt = 2; c.c[0] = 0; c.i[0] = k; c.c[1] = 1; c.i[1] = 0; }
+  if (c.cnt == 1) { c.c[1] = c.c[0]; c.i[1] = c.i[0]; }
+  return c;
+}
+
+// eig (PER_PATCH): per patch S_x, S_y, S_z (M x M), l_x, l_y, l_z (M);
+// otherwise (EO) the even/odd halves of the Cartesian S and the eigenvalues.
+template <typename T, int K, bool PER_PATCH>
+__global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r, T* __restrict__ W,
+                                                        const T* __restrict__ eig, T scale, int n) {
+  using P = WavePatch<K>;
+  constexpr int k = P::k, M = P::M, M2 = P::M2, M3 = P::M3, ROUNDS = P::ROUNDS;
+  constexpr int K3 = K * K * K;
+  constexpr bool EO = !PER_PATCH;
+  __shared__ T t[M3];
+  const int lane = threadIdx.x;
+  const int nv = n - 1;
+  const int64_t pid = blockIdx.x;
+  const int vx = 1 + (int)(pid % nv), vy = 1 + (int)((pid / nv) % nv), vz = 1 + (int)(pid / ((int64_t)nv * nv));
+  const T *Sx, *Sy, *Sz, *lx, *ly, *lz;
+  if (PER_PATCH) {
+    const T* base = eig + pid * (3 * M2 + 3 * M);
+    Sx = base; Sy = base + M2; Sz = base + 2 * M2;
+    lx = base + 3 * M2; ly = lx + M; lz = ly + M;
+  } else {
+    Sx = Sy = Sz = eig;
+    lx = ly = lz = eig + P::NE * (P::C + 1) + P::NO * P::C;
+  }
+  const int64_t c0 = (vx - 1) + (int64_t)n * ((vy - 1) + (int64_t)n * (vz - 1));
+  const T* __restrict__ rc = r + c0 * K3;
+  const int64_t sy_cells = (int64_t)n * K3, sz_cells = (int64_t)n * n * K3;
+
+  // (1) z-pencils (x, y): assemble, S_z^T, store
+#pragma unroll
+  for (int ro = 0; ro < ROUNDS; ++ro) {
+    const int l = lane + 64 * ro;
+    if (l < M2) {
+      const int x = l % M, y = l / M;
+      const AxisCopies cx = wave_axis_copies<K>(x), cy = wave_axis_copies<K>(y);
+      T v[M], w[M];
+#pragma unroll
+      for (int z = 0; z < M; ++z) {
+        const AxisCopies cz = wave_axis_copies<K>(z);
+        T zs = T(0);
+#pragma unroll
+        for (int sz = 0; sz < 2; ++sz) {
+          if (sz >= cz.cnt) break;
+          T ys = T(0);
+#pragma unroll
+          for (int sy = 0; sy < 2; ++sy) {
+            if (sy >= cy.cnt) break;
+            const T* cb = rc + cz.c[sz] * sz_cells + cy.c[sy] * sy_cells + K * (cy.i[sy] + K * cz.i[sz]);
+            T xs = cb[cx.c[0] * K3 + cx.i[0]];
+            if (cx.cnt == 2) xs += cb[cx.c[1] * K3 + cx.i[1]];
+            ys = sy == 0 ? xs : ys + xs;
+          }
+          zs = sz == 0 ? ys : zs + ys;
+        }
+        v[z] = zs;
+      }
+      line_apply<T, M, EO, true>(Sz, v, w);
+#pragma unroll
+      for (int z = 0; z < M; ++z) t[z * M2 + y * M + x] = w[z];
+    }
+  }
+  wave_sync();
+  // (2) y-pencils (x, z): S_y^T
+#pragma unroll
+  for (int ro = 0; ro < ROUNDS; ++ro) {
+    const int l = lane + 64 * ro;
+    if (l < M2) {
+      const int x = l % M, z = l / M;
+      T v[M], w[M];
+#pragma unroll
+      for (int a = 0; a < M; ++a) v[a] = t[z * M2 + a * M + x];
+      line_apply<T, M, EO, true>(Sy, v, w);
+#pragma unroll
+      for (int a = 0; a < M; ++a) t[z * M2 + a * M + x] = w[a];
+    }
+  }
+  wave_sync();
+  // (3) x-pencils (y, z): S_x^T, scale by (l_x + l_y + l_z)^{-1}, S_x
+#pragma unroll
+  for (int ro = 0; ro < ROUNDS; ++ro) {
+    const int l = lane + 64 * ro;
+    if (l < M2) {
+      const int y = l % M, z = l / M;
+      T v[M], w[M];
+#pragma unroll
+      for (int a = 0; a < M; ++a) v[a] = t[z * M2 + y * M + a];
+      line_apply<T, M, EO, true>(Sx, v, w);
+      const T lyz = ly[y] + lz[z];
+#pragma unroll
+      for (int a = 0; a < M; ++a) w[a] *= scale * recip(lx[a] + lyz);
+      line_apply<T, M, EO, false>(Sx, w, v);
+#pragma unroll
+      for (int a = 0; a < M; ++a) t[z * M2 + y * M + a] = v[a];
+    }
+  }
+  wave_sync();
+  // (4) y-pencils: S_y
+#pragma unroll
+  for (int ro = 0; ro < ROUNDS; ++ro) {
+    const int l = lane + 64 * ro;
+    if (l < M2) {
+      const int x = l % M, z = l / M;
+      T v[M], w[M];
+#pragma unroll
+      for (int a = 0; a < M; ++a) v[a] = t[z * M2 + a * M + x];
+      line_apply<T, M, EO, false>(Sy, v, w);
+#pragma unroll
+      for (int a = 0; a < M; ++a) t[z * M2 + a * M + x] = w[a];
+    }
+  }
+  wave_sync();
+  // (5) z-pencils: S_z, then the slot-split output: node a of an axis lies in
+  // slot 0 at a (a <= k-1) and in slot 1 at a - (k-1) (a >= k-1)
+  constexpr int k3 = k * k * k;
+  T* wp = W + pid * (8 * k3);
+#pragma unroll
+  for (int ro = 0; ro < ROUNDS; ++ro) {
+    const int l = lane + 64 * ro;
+    if (l < M2) {
+      const int x = l % M, y = l / M;
+      T v[M], w[M];
+#pragma unroll
+      for (int z = 0; z < M; ++z) v[z] = t[z * M2 + y * M + x];
+      line_apply<T, M, EO, false>(Sz, v, w);
+#pragma unroll
+      for (int z = 0; z < M; ++z) {
+#pragma unroll
+        for (int szs = 0; szs < 2; ++szs) {
+          const int jz = szs ? z - (k - 1) : z;
+          if (jz < 0 || jz >= k) continue;
+#pragma unroll
+          for (int sys = 0; sys < 2; ++sys) {
+            const int jy = sys ? y - (k - 1) : y;
+            if (jy < 0 || jy >= k) continue;
+#pragma unroll
+            for (int sxs = 0; sxs < 2; ++sxs) {
+              const int jx = sxs ? x - (k - 1) : x;
+              if (jx < 0 || jx >= k) continue;
+              wp[(sxs + 2 * sys + 4 * szs) * k3 + jx + k * (jy + k * jz)] = w[z];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+bool patch_wave_supported(const fe_problem* p, bool per_patch) {
+  return p->dim == 3 && p->k >= 4 && p->k <= 8 && (per_patch || p->co.off_Seo >= 0);
+}
+
+template <typename T, int K>
+static fe_status patch_wave_typed(const Level& L, const T* r, T* W, const T* eig, bool per_patch, T scale,
+                                  hipStream_t s) {
+  const int64_t nv = L.n - 1, np = nv * nv * nv;
+  if (np == 0) return FE_OK;
+  ProfScope ps("fdm_patch", s);
+  if (per_patch)
+    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, true>), dim3((unsigned)np), dim3(64), 0, s, r, W, eig, scale, L.n);
+  else
+    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, false>), dim3((unsigned)np), dim3(64), 0, s, r, W, eig, scale, L.n);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+// eig: per-patch eigen-data (per_patch) or null (the Cartesian even/odd table is used)
+fe_status launch_patch_wave(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
+                            bool per_patch, double scale, fe_dtype dt, hipStream_t s) {
+  switch (p->K) {
+#define FE_WAVE_CASE(KV)                                                                                   \
+  case KV:                                                                                                 \
+    if (dt == FE_F64)                                                                                      \
+      return patch_wave_typed<double, KV>(L, (const double*)r, (double*)W,                                 \
+                                          per_patch ? (const double*)eig                                   \
+                                                    : p->coef64.as<double>() + p->co.off_Seo,              \
+                                          per_patch, scale, s);                                            \
+    return patch_wave_typed<float, KV>(L, (const float*)r, (float*)W,                                      \
+                                       per_patch ? (const float*)eig : p->coef32.as<float>() + p->co.off_Seo, \
+                                       per_patch, (float)scale, s);
+    FE_WAVE_CASE(5)
+    FE_WAVE_CASE(6)
+    FE_WAVE_CASE(7)
+    FE_WAVE_CASE(8)
+    FE_WAVE_CASE(9)
+#undef FE_WAVE_CASE
+    default:
+      return fail(FE_EUNSUPPORTED, "wave patch inverse: unsupported degree");
+  }
+}
+
+}  // namespace fe
