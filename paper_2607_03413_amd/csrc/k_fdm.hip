@@ -8,13 +8,16 @@
 // S_a^T M_a S_a = I (one pair per axis), A_p^{-1} = (S x S x S) (L + L + L)^{-1}
 // (S x S x S)^T.
 //
-// Two kernels:
-//  (1) one group of m^2 threads per patch: each thread sums the copies of one
-//      z-pencil of patch nodes (cascade order, straight from the cell-wise
-//      residual, so G^T r is never formed), applies S^T along z, y, x
-//      (pencils re-oriented through LDS), divides by the eigenvalue sums,
-//      applies S along x, y, z, and writes the m^d patch solution to a
-//      patch-major scratch buffer;
+// Dispatch (launch_patch_inverse): the 3D Cartesian k = 2, 3 case runs the
+// fused single-pass kernel (k_fdm_fused.hip); otherwise two passes:
+//  (1) patch solutions: for k >= 4 one wavefront per patch (k_fdm_patch3_wave,
+//      k_fdm_wave.hip); for k <= 3 with per-patch factors, k_fdm_patch3 below:
+//      one group of m^2 threads per patch sums the copies of one z-pencil of
+//      patch nodes (cascade order, straight from the cell-wise residual, so
+//      G^T r is never formed), applies S^T along z, y, x (pencils re-oriented
+//      through LDS), divides by the eigenvalue sums, applies S along x, y, z;
+//      3D solutions are written split by cell slot (8 blocks of k^3 per patch),
+//      2D ones patch-major;
 //  (2) one thread per cell-wise entry sums the solutions of the (at most 2^d)
 //      patches containing its node, in a fixed order that depends only on the
 //      node, so every copy receives bit-identical values (continuity).
@@ -409,108 +412,11 @@ __global__ void __launch_bounds__(256) k_fdm_sum(const T* __restrict__ W, T* __r
   z[e] = s;
 }
 
-// Kernel (2), 3D, staged: a block owns TXC consecutive cells of one x-row
-// (fixed cy, cz).  The patches touching them have vy in {cy, cy+1}, vz in
-// {cz, cz+1} and vx in [cx0, cx0+TXC]; for each (vy, vz) their solutions
-// are one contiguous run of the patch-major buffer, copied to LDS with
-// coalesced loads.  Each entry then sums its (at most 8) contributions in
-// the fixed order (vz, vy, vx ascending), which depends only on the node.
-template <int K>
-struct SumTile {
-  static constexpr int k = K - 1;
-  static constexpr int M = 2 * k - 1;
-  static constexpr int K3 = K * K * K;
-  static constexpr int M3 = M * M * M;
-  static constexpr int TXC = (512 / K3) > 0 ? (512 / K3) : 1;
-};
-
-template <typename T, int K>
-__global__ void __launch_bounds__(256) k_fdm_sum3_staged(const T* __restrict__ W, T* __restrict__ z, int n,
-                                                         int segs) {
-  using TL = SumTile<K>;
-  constexpr int k = TL::k, M = TL::M, K3 = TL::K3, M3 = TL::M3, TXC = TL::TXC;
-  constexpr int NPX = TXC + 1;
-  __shared__ T sw[4 * NPX * M3];
-  const int nv = n - 1;
-  const int seg = blockIdx.x % segs;
-  const int row = blockIdx.x / segs;
-  const int cy = row % n, cz = row / n;
-  const int cx0 = seg * TXC;
-  const int ncell = min(TXC, n - cx0);
-  // patch runs: vx in [vlo, vhi]
-  const int vlo = max(cx0, 1), vhi = min(cx0 + ncell, nv);
-  const int npx = vhi - vlo + 1;   // may be <= 0 when n == 1
-  for (int q = 0; q < 4; ++q) {
-    const int vy = cy + (q & 1), vz = cz + (q >> 1);
-    if (vy < 1 || vy > nv || vz < 1 || vz > nv || npx <= 0) continue;
-    const T* src = W + ((int64_t)(vlo - 1) + (int64_t)nv * ((vy - 1) + (int64_t)nv * (vz - 1))) * M3;
-    T* dst = sw + q * NPX * M3;
-    for (int i = threadIdx.x; i < npx * M3; i += blockDim.x) dst[i] = src[i];
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < ncell * K3; e += blockDim.x) {
-    const int cl = e / K3;
-    const int loc = e - cl * K3;
-    const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
-    const int cx = cx0 + cl;
-    const AxisPatches px = axis_patches<K>(k * cx + ix, n);
-    const AxisPatches py = axis_patches<K>(k * cy + iy, n);
-    const AxisPatches pz = axis_patches<K>(k * cz + iz, n);
-    T s = T(0);
-    for (int a = 0; a < pz.cnt; ++a)
-      for (int b = 0; b < py.cnt; ++b) {
-        const int q = (pz.v[a] - cz) * 2 + (py.v[b] - cy);
-        const T* base = sw + q * NPX * M3 + M * (py.o[b] + M * pz.o[a]);
-        for (int c = 0; c < px.cnt; ++c) s += base[(px.v[c] - vlo) * M3 + px.o[c]];
-      }
-    z[((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc] = s;
-  }
-}
-
-// Kernel (2), 3D, node-centric: one thread per global node sums the patch
-// solutions at that node (each value of the patch-major buffer is read
-// exactly once, consecutive threads read consecutive patch entries) in the
-// order (vz, vy, vx ascending), and writes the sum to every cell copy.
-template <typename T, int K>
-__global__ void __launch_bounds__(256) k_fdm_sum_nodes3(const T* __restrict__ W, T* __restrict__ z, int n,
-                                                        int64_t n_nodes) {
-  constexpr int k = K - 1;
-  constexpr int M = 2 * k - 1;
-  constexpr int M3 = M * M * M;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_nodes) return;
-  const int N = k * n + 1;
-  const int gx = (int)(g % N);
-  const int64_t t = g / N;
-  const int gy = (int)(t % N), gz = (int)(t / N);
-  const int nv = n - 1;
-  const AxisPatches px = axis_patches<K>(gx, n), py = axis_patches<K>(gy, n), pz = axis_patches<K>(gz, n);
-  T s = T(0);
-  for (int a = 0; a < pz.cnt; ++a)
-    for (int b = 0; b < py.cnt; ++b) {
-      const int64_t rowp = (int64_t)nv * ((py.v[b] - 1) + (int64_t)nv * (pz.v[a] - 1));
-      const int off = M * (py.o[b] + M * pz.o[a]);
-      for (int c = 0; c < px.cnt; ++c) s += W[(rowp + px.v[c] - 1) * M3 + off + px.o[c]];
-    }
-  const AxisCopies ax = axis_copies<K>(gx, n), ay = axis_copies<K>(gy, n), az = axis_copies<K>(gz, n);
-  for (int sz = 0; sz < az.cnt; ++sz)
-    for (int sy = 0; sy < ay.cnt; ++sy)
-      for (int sx = 0; sx < ax.cnt; ++sx) z[copy_addr<K, 3>(ax, ay, az, sx, sy, sz, n)] = s;
-}
-
-template <int K, typename T>
-constexpr bool sum_staged_fits() {
-  return 4 * (SumTile<K>::TXC + 1) * SumTile<K>::M3 * sizeof(T) <= 64 * 1024;
-}
-
-bool patch_mfma_supported(const fe_problem* p);
 bool fused_patch_supported(const fe_problem* p, bool per_patch);
 bool patch_wave_supported(const fe_problem* p, bool per_patch);
 fe_status launch_patch_wave(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
                             bool per_patch, double scale, fe_dtype dt, hipStream_t s);
 fe_status launch_patch_fused(const fe_problem* p, int level, const void* r, void* z, fe_dtype dt, hipStream_t s);
-fe_status launch_patch_mfma(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
-                            bool per_patch, double scale, fe_dtype dt, hipStream_t s);
 
 size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt) {
   const Level& L = level_of(p, level);
@@ -532,8 +438,6 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
     const int64_t np = nv * nv * nv;
     if (np > 0 && patch_wave_supported(p, per_patch)) {
       FE_CHECK(launch_patch_wave(p, L, r, W, eig, per_patch, (double)scale, std::is_same<T, double>::value ? FE_F64 : FE_F32, s));
-    } else if (np > 0 && patch_mfma_supported(p)) {
-      FE_CHECK(launch_patch_mfma(p, L, r, W, eig, per_patch, (double)scale, std::is_same<T, double>::value ? FE_F64 : FE_F32, s));
     } else if (np > 0) {
       constexpr int PPB = PatchLayout<K>::PPB;
       constexpr int THREADS = PatchLayout<K>::THREADS;

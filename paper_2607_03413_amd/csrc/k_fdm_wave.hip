@@ -136,7 +136,12 @@ __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r,
   __shared__ T t[M3];
   const int lane = threadIdx.x;
   const int nv = n - 1;
-  const int64_t pid = blockIdx.x;
+  // XCD-aware order: blocks are dealt to the 8 XCDs round-robin; give each XCD
+  // a contiguous range of patches so that neighbouring patches, which read the
+  // same cells, share an L2
+  const int64_t nb = gridDim.x, q8 = nb >> 3, rem = nb & 7;
+  const int64_t xcd = blockIdx.x & 7;
+  const int64_t pid = xcd * q8 + (xcd < rem ? xcd : rem) + (blockIdx.x >> 3);
   const int vx = 1 + (int)(pid % nv), vy = 1 + (int)((pid / nv) % nv), vz = 1 + (int)(pid / ((int64_t)nv * nv));
   const T *Sx, *Sy, *Sz, *lx, *ly, *lz;
   if (PER_PATCH) {
