@@ -128,8 +128,9 @@ def kernel_bytes(P, dt_bytes):
     k, n = P.degree, P.n
     n_patches = (n - 1) ** 3
     vec = P.len * dt_bytes
-    # patch solutions split by cell slot: 8 blocks of k^3 per patch
-    wbuf = n_patches * 8 * k ** 3 * dt_bytes
+    # patch solutions: k <= 3 split by cell slot (8 blocks of k^3 per patch),
+    # k >= 4 patch-major ((2k-1)^3 per patch)
+    wbuf = n_patches * (8 * k ** 3 if k <= 3 else (2 * k - 1) ** 3) * dt_bytes
     # the fused patch inverse reads r and writes z once
     return {"apply": 2 * vec, "fdm_patch": vec + wbuf, "fdm_sum": wbuf + vec, "fdm_fused": 2 * vec}
 

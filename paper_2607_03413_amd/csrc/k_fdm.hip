@@ -16,8 +16,8 @@
 //      patch nodes (cascade order, straight from the cell-wise residual, so
 //      G^T r is never formed), applies S^T along z, y, x (pencils re-oriented
 //      through LDS), divides by the eigenvalue sums, applies S along x, y, z;
-//      3D solutions are written split by cell slot (8 blocks of k^3 per patch),
-//      2D ones patch-major;
+//      its 3D solutions are written split by cell slot (8 blocks of k^3 per
+//      patch), all others patch-major;
 //  (2) one thread per cell-wise entry sums the solutions of the (at most 2^d)
 //      patches containing its node, in a fixed order that depends only on the
 //      node, so every copy receives bit-identical values (continuity).
@@ -412,6 +412,57 @@ __global__ void __launch_bounds__(256) k_fdm_sum(const T* __restrict__ W, T* __r
   z[e] = s;
 }
 
+// Kernel (2), 3D, patch-major solutions (k >= 4): one thread per cell-wise
+// entry, a fixed 2 x 2 x 2 set of candidate patches per entry so that lanes do
+// not diverge.  Along each axis the node g = k c + i lies strictly inside
+// patch c (offset k-1+i) when i < k and inside patch c+1 (offset i-1) when
+// i > 0; candidates outside 1..n-1 or not containing the node contribute 0.
+// The sum runs over (z, y, x) patch candidates in ascending vertex order,
+// which depends only on the node: all copies receive identical values.
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n,
+                                                     int64_t len) {
+  constexpr int k = K - 1;
+  constexpr int M = 2 * k - 1;
+  constexpr int MP = M * M * M;
+  constexpr int NL = K * K * K;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const int64_t cell = e / NL;
+  const int loc = (int)(e - cell * NL);
+  const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+  const int cx = (int)(cell % n);
+  const int64_t t = cell / n;
+  const int cy = (int)(t % n), cz = (int)(t / n);
+  const int nv = n - 1;
+  // candidate c = 0: vertex = cell (offset k-1+i), c = 1: vertex = cell+1 (offset i-1)
+  const int c3[3] = {cx, cy, cz}, i3[3] = {ix, iy, iz};
+  int vtx[3][2], off[3][2];
+  bool ok[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vtx[a][0] = c3[a];
+    off[a][0] = k - 1 + i3[a];
+    ok[a][0] = i3[a] < k && c3[a] >= 1;
+    vtx[a][1] = c3[a] + 1;
+    off[a][1] = i3[a] - 1;
+    ok[a][1] = i3[a] > 0 && c3[a] + 1 <= nv;
+  }
+  T s = T(0);
+#pragma unroll
+  for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const bool use = ok[2][bz] && ok[1][by] && ok[0][bx];
+        const int64_t pid = (vtx[0][bx] - 1) + (int64_t)nv * ((vtx[1][by] - 1) + (int64_t)nv * (vtx[2][bz] - 1));
+        const int o = off[0][bx] + M * (off[1][by] + M * off[2][bz]);
+        if (use) s += W[pid * MP + o];   // masked load: no access for absent patches
+      }
+  z[e] = s;
+}
+
 bool fused_patch_supported(const fe_problem* p, bool per_patch);
 bool patch_wave_supported(const fe_problem* p, bool per_patch);
 fe_status launch_patch_wave(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
@@ -424,7 +475,7 @@ size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt) {
   const int64_t M = 2 * p->k - 1;
   const int64_t k = p->k;
   const int64_t np = p->dim == 3 ? nv * nv * nv : nv * nv;
-  // 3D: slot-split layout, 8 k^3 per patch; 2D: patch-major, M^2 per patch
+  // 3D: slot-split layout, 8 k^3 per patch (k >= 4: patch-major M^3 <= 8 k^3); 2D: patch-major, M^2 per patch
   const int64_t mp = p->dim == 3 ? 8 * k * k * k : M * M;
   return (size_t)(np * mp) * (dt == FE_F64 ? 8 : 4);
 }
@@ -451,8 +502,12 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
       FE_HIP_CHECK(hipGetLastError());
     }
     ProfScope ps2("fdm_sum", s);
-    hipLaunchKernelGGL((k_fdm_sum_slots3<T, K>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
-                       L.len);
+    if (patch_wave_supported(p, per_patch))   // patch-major solutions
+      hipLaunchKernelGGL((k_fdm_sum_pm3<T, K>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
+                         L.len);
+    else                                      // slot-split solutions
+      hipLaunchKernelGGL((k_fdm_sum_slots3<T, K>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z,
+                         L.n, L.len);
   } else {
     const int64_t np = nv * nv;
     if (np > 0) {

@@ -13,8 +13,8 @@
 //   * y: S_y^T; x: S_x^T, scaling by the inverse eigenvalue sums, S_x; y: S_y,
 //     each an in-place pass over LDS lines (no two lanes share a line, so a
 //     wavefront-level fence between the passes suffices);
-//   * z: S_z in registers, and the result is written slot by slot (the k^3
-//     patch nodes inside each of the 8 cells) for the slot-sum pass.
+//   * z: S_z in registers, and the patch solution is written patch-major
+//     (m^3 values per patch) for the summing pass.
 // With the exact Cartesian factors the mirror symmetry of the two-cell patch
 // is used: every eigenvector is even or odd about the middle node, so a
 // line costs (c+1)^2 + c^2 instead of m^2 FMAs (c = k-1).
@@ -239,38 +239,19 @@ __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r,
     }
   }
   wave_sync();
-  // (5) z-pencils: S_z, then the slot-split output: node a of an axis lies in
-  // slot 0 at a (a <= k-1) and in slot 1 at a - (k-1) (a >= k-1)
-  constexpr int k3 = k * k * k;
-  T* wp = W + pid * (8 * k3);
+  // (5) z-pencils: S_z, then the patch solution, patch-major (m^3 values, x
+  // fastest): consecutive lanes store consecutive values
+  T* wp = W + pid * M3;
 #pragma unroll
   for (int ro = 0; ro < ROUNDS; ++ro) {
     const int l = lane + 64 * ro;
     if (l < M2) {
-      const int x = l % M, y = l / M;
       T v[M], w[M];
 #pragma unroll
-      for (int z = 0; z < M; ++z) v[z] = t[z * M2 + y * M + x];
+      for (int z = 0; z < M; ++z) v[z] = t[z * M2 + l];
       line_apply<T, M, EO, false>(Sz, v, w);
 #pragma unroll
-      for (int z = 0; z < M; ++z) {
-#pragma unroll
-        for (int szs = 0; szs < 2; ++szs) {
-          const int jz = szs ? z - (k - 1) : z;
-          if (jz < 0 || jz >= k) continue;
-#pragma unroll
-          for (int sys = 0; sys < 2; ++sys) {
-            const int jy = sys ? y - (k - 1) : y;
-            if (jy < 0 || jy >= k) continue;
-#pragma unroll
-            for (int sxs = 0; sxs < 2; ++sxs) {
-              const int jx = sxs ? x - (k - 1) : x;
-              if (jx < 0 || jx >= k) continue;
-              wp[(sxs + 2 * sys + 4 * szs) * k3 + jx + k * (jy + k * jz)] = w[z];
-            }
-          }
-        }
-      }
+      for (int z = 0; z < M; ++z) wp[z * M2 + l] = w[z];
     }
   }
 }
