@@ -233,7 +233,9 @@ def bench_deformed(fe, k, n, n_train, train_meshes, epochs, with_solve=True):
                  ("fp32_chebfdm_averaged", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
                                                            factors=1, nu_pre=1, nu_post=1, tol=1e-10)),
                  ("fp32_chebfdm_learned", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
-                                                          factors=2, nu_pre=1, nu_post=1, tol=1e-10)))
+                                                          factors=2, nu_pre=1, nu_post=1, tol=1e-10)),
+                 ("fp32_chebfdm_bestfit", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
+                                                          factors=3, nu_pre=1, nu_post=1, tol=1e-10)))
         for name, opts in cases:
             x = P.cellvec()
             P.pcg_solve(b, x, opts, raise_on_error=False)

@@ -123,7 +123,10 @@ fe_status fe_apply_level(const fe_problem* prob, int level, const void* x_cell, 
  * diagonalization with 1D generalized eigenpairs (K S = M S Lambda).
  *   factors = 0: exact separable factors (Cartesian mesh only),
  *   factors = 1: per-patch averaged-geometry factors (deformed mesh),
- *   factors = 2: per-patch learned factors (after fe_mlp_train).
+ *   factors = 2: per-patch learned factors (after fe_mlp_train),
+ *   factors = 3: per-patch best Kronecker-sum fit of A_p (the learned model's
+ *                training target, computed per patch at setup; the reference
+ *                the learned factors approximate).
  * r: dual cell-wise; z: primal cell-wise (continuous, copies bit-identical).
  * The result depends only on G^T r.  r and z must not alias. */
 fe_status patch_fdm_inverse(const fe_problem* prob, const void* r_cell, void* z_cell, fe_dtype dt,

@@ -368,7 +368,7 @@ fe_status patch_fdm_inverse_level(const fe_problem* cp, int level, const void* r
   FE_CHECK(check_ptr(r, "r_cell"));
   FE_CHECK(check_ptr(z, "z_cell"));
   if (r == z) return fail(FE_EINVAL, "r and z must not alias");
-  if (factors < 0 || factors > 2) return fail(FE_EINVAL, "factors must be 0, 1 or 2");
+  if (factors < 0 || factors > 3) return fail(FE_EINVAL, "factors must be 0, 1, 2 or 3");
   if (factors == 0 && p->desc.geometry != FE_GEOM_CARTESIAN)
     return fail(FE_EINVAL, "exact separable factors need the Cartesian mesh");
   if (factors != 0 && p->desc.geometry != FE_GEOM_DEFORMED)

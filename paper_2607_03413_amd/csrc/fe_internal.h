@@ -86,8 +86,8 @@ struct Level {
   // deformed geometry: per-cell quadrature metric (6 per point), per dtype
   DeviceBuf metric64, metric32;
   // deformed geometry: per-patch 1D eigen-data, per factor mode and dtype
-  DeviceBuf patch_eig64[3], patch_eig32[3];
-  bool patch_eig_ready[3] = {false, false, false};
+  DeviceBuf patch_eig64[4], patch_eig32[4];
+  bool patch_eig_ready[4] = {false, false, false, false};
   // inverse assembled diagonal with valence and Dirichlet mask baked in
   DeviceBuf dinv64, dinv32;
   bool dinv_ready = false;

@@ -768,7 +768,7 @@ fe_status patch_weights(fe_problem* p, int level, int mode, DeviceBuf& weights, 
 
 fe_status setup_patch_factors(fe_problem* p, int level, int mode, hipStream_t s) {
   if (p->desc.geometry != FE_GEOM_DEFORMED) return fail(FE_EINVAL, "per-patch factors need the deformed geometry");
-  if (mode != 1 && mode != 2) return fail(FE_EINVAL, "factor mode must be 1 or 2");
+  if (mode < 1 || mode > 3) return fail(FE_EINVAL, "factor mode must be 1, 2 or 3");
   DeviceBuf weights;
   FE_CHECK(patch_weights(p, level, mode, weights, s));
   FE_DISPATCH_K(p->K, return eig_from_weights<KK>(p, level, mode, weights.as<double>(), s));

@@ -592,8 +592,30 @@ __global__ void __launch_bounds__(256) k_weights_from_log(const float* __restric
   if (e < n) w[e] = exp((double)y[e] + log_h3);
 }
 
+__global__ void __launch_bounds__(256) k_weights_from_log64(const double* __restrict__ y, double log_h3,
+                                                            double* __restrict__ w, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) w[e] = exp(y[e] + log_h3);
+}
+
+// mode 1: averaged-geometry weights; mode 2: MLP prediction; mode 3: the
+// per-patch best Kronecker-sum fit itself (the MLP's training target).
 fe_status patch_weights(fe_problem* p, int level, int mode, DeviceBuf& weights, hipStream_t s) {
   if (mode == 1) return averaged_patch_weights(p, level, weights, s);
+  if (mode == 3) {
+    Level& L = p->levels[level];
+    const int64_t nv = L.n - 1, np = nv * nv * nv;
+    FE_CHECK(weights.alloc(std::max<int64_t>(np, 1) * 12 * sizeof(double)));
+    if (np == 0) return FE_OK;
+    DeviceBuf tg;
+    FE_CHECK(tg.alloc(np * 12 * sizeof(double)));
+    FE_CHECK(fit_targets(p, level, 20, tg.as<double>(), s));
+    hipLaunchKernelGGL(k_weights_from_log64, dim3(nblk(np * 12)), dim3(256), 0, s, tg.as<double>(),
+                       std::log(L.h) / 3.0, weights.as<double>(), np * 12);
+    FE_HIP_CHECK(hipGetLastError());
+    FE_HIP_CHECK(hipStreamSynchronize(s));
+    return FE_OK;
+  }
   if (!p->mlp_ready) return fail(FE_EINVAL, "learned factors need a trained model (fe_mlp_train or fe_mlp_set_params)");
   Level& L = p->levels[level];
   const int64_t nv = L.n - 1, np = nv * nv * nv;

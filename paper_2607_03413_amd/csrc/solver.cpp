@@ -310,7 +310,7 @@ static fe_status check_opts(const fe_problem* p, const fe_pcg_opts* o) {
     return fail(FE_EINVAL, "exact separable factors need the Cartesian mesh");
   if (o->smoother == FE_SMOOTH_CHEB_FDM && o->factors != 0 && p->desc.geometry != FE_GEOM_DEFORMED)
     return fail(FE_EINVAL, "per-patch factors need the deformed geometry");
-  if (o->factors < 0 || o->factors > 2) return fail(FE_EINVAL, "bad factors");
+  if (o->factors < 0 || o->factors > 3) return fail(FE_EINVAL, "bad factors");
   if (o->nu_pre < 0 || o->nu_post < 0 || o->maxit < 0) return fail(FE_EINVAL, "negative counts");
   if (!(o->tol >= 0.0)) return fail(FE_EINVAL, "bad tolerance");
   return FE_OK;
