@@ -147,6 +147,39 @@ __device__ __forceinline__ void contract_axis(T (&w)[M][M][M], const T* __restri
     }
 }
 
+// Workgroup barrier without a memory fence.  A fence here would also wait for
+// every copy still in flight into LDS (vmcnt(0)) and serialize the staging
+// pipeline; instead each wavefront waits for the copies it needs explicitly
+// (wait_vmcnt_le), its LDS operations complete before the barrier
+// (lgkmcnt(0)), and the "memory" clobber keeps the compiler from moving
+// memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Value of lane - 1 (0 in lane 0): a DPP wavefront shift, no LDS traffic.
+__device__ __forceinline__ float lane_shift_up(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_shift_up(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wait until at most `n` vector memory operations of this wavefront are
+// outstanding (s_waitcnt vmcnt(n), n a compile-time constant after unrolling;
+// expcnt and lgkmcnt left at their maxima).
+__device__ __forceinline__ void wait_vmcnt_le(int n) {
+  switch (n) {
+#define FE_VMCNT_CASE(N) \
+    case N: __builtin_amdgcn_s_waitcnt(((N) & 0xF) | (((N) >> 4) << 14) | (0x7 << 4) | (0xF << 8)); break;
+    FE_VMCNT_CASE(0) FE_VMCNT_CASE(5) FE_VMCNT_CASE(10) FE_VMCNT_CASE(15) FE_VMCNT_CASE(20)
+    FE_VMCNT_CASE(25) FE_VMCNT_CASE(30) FE_VMCNT_CASE(40)
+#undef FE_VMCNT_CASE
+    default: __builtin_amdgcn_s_waitcnt(0x0F70); break;   // vmcnt(0)
+  }
+}
+
 // Slice s of patch level vz: cell layer and z-local index (see the header).
 template <int K>
 __device__ __forceinline__ void slice_of(int s, int vz, int& layer, int& iz) {
@@ -260,8 +293,14 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
   constexpr int k = FP::k, M = FP::M, WY = FP::WY, K2 = FP::K2, K3 = K2 * K;
   constexpr int NBUF = FP::NBUF, SLICE = FP::SLICE, XPLANE = FP::XPLANE;
   constexpr int NS = 2 * k;   // slices per level
-  __shared__ __attribute__((aligned(16))) T sbuf[NBUF * SLICE];
+  // three distinct LDS arrays (rather than one) let the compiler see that a
+  // read of one buffer does not depend on the copies still landing in another
+  __shared__ __attribute__((aligned(16))) T sbuf0[SLICE];
+  __shared__ __attribute__((aligned(16))) T sbuf1[SLICE];
+  __shared__ __attribute__((aligned(16))) T sbuf2[NBUF > 2 ? SLICE : 1];
+  auto buf = [&](int j) -> T* { return j == 0 ? sbuf0 : (j == 1 ? sbuf1 : sbuf2); };
   __shared__ T xch[XPLANE * 64 * WY];
+  static_assert(XPLANE * 64 * WY <= SLICE, "the overlap exchange also uses a slice buffer");
 
   // XCD-aware block order: consecutive logical tiles land on the same XCD
   // (blocks are dealt to the 8 XCDs round-robin), so that the halo rows and
@@ -288,7 +327,7 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
   // slices 0 .. NBUF-1 of the first level are in flight before the loop
   if (C0 >= 1 && C0 <= n - 1) {
 #pragma unroll
-    for (int s = 0; s < NBUF; ++s) stage_slice<T, K>(sbuf + s * SLICE, r, s, C0, X0, Y0, n, tid);
+    for (int s = 0; s < NBUF; ++s) stage_slice<T, K>(buf(s), r, s, C0, X0, Y0, n, tid);
   }
 
   for (int vz = C0; vz <= C1; ++vz) {
@@ -296,27 +335,31 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
     const bool level_ok = vz >= 1 && vz <= n - 1;   // uniform over the block
     const bool next_ok = vz + 1 <= C1 && vz + 1 <= n - 1;
     if (level_ok) {
-      // (1) patch residual R_p G^T r, NBUF slices per round
+      // (1) patch residual R_p G^T r, slice by slice: slice s is read from
+      // buffer s % NBUF, which then receives slice s + NBUF, so that NBUF - 1
+      // copies stay in flight while a slice is summed
 #pragma unroll
-      for (int s0 = 0; s0 < NS; s0 += NBUF) {
-        if (s0 > 0) {
-          __syncthreads();   // readers of the previous round are done
-#pragma unroll
-          for (int j = 0; j < NBUF; ++j)
-            if (s0 + j < NS) stage_slice<T, K>(sbuf + j * SLICE, r, s0 + j, vz, X0, Y0, n, tid);
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+      for (int sl = 0; sl < NS; ++sl) {
+        // wait until slice sl has landed.  Loads (copies included) complete in
+        // issue order, so while slice sl is outstanding every copy issued after
+        // it is too: allowing that many outstanding operations is safe even with
+        // stores of the previous level, which may complete out of order, still
+        // in flight (they only make the wait longer).
+        constexpr int DPW = FP::DMA ? (FP::NYC * FP::NCH) / WY : 0;
+        const int later = (sl + NBUF - 1 < NS - 1 ? sl + NBUF - 1 : NS - 1) - sl;
+        if (FP::DMA) wait_vmcnt_le(later * DPW);
+        lds_barrier();
         if (pxy) {
-#pragma unroll
-          for (int j = 0; j < NBUF; ++j)
-            if (s0 + j < NS) {
-              // the base is opaque to the compiler so that every read of this
-              // buffer is one base plus an immediate offset below 64 KB
-              lds_ptr<T> lb = (lds_ptr<T>)(sbuf + j * SLICE + lane_off);
-              asm volatile("" : "+v"(lb));
-              pull_slice<T, K, M>(w, lb, s0 + j);
-            }
+          // the lane offset is made opaque so that it is recomputed here
+          // instead of three buffer bases being kept live across the level loop
+          int off = lane_off;
+          asm volatile("" : "+v"(off));
+          lds_ptr<T> lb = (lds_ptr<T>)(buf(sl % NBUF)) + off;
+          pull_slice<T, K, M>(w, lb, sl);
+        }
+        if (sl + NBUF < NS) {
+          lds_barrier();   // readers of this buffer are done
+          stage_slice<T, K>(buf(sl % NBUF), r, sl + NBUF, vz, X0, Y0, n, tid);
         }
       }
       if (!pxy) {
@@ -327,11 +370,12 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
 #pragma unroll
             for (int ax = 0; ax < M; ++ax) w[az][ay][ax] = T(0);
       }
-      // the next level's first slices are fetched while this level computes
-      __syncthreads();
+      // the next level's first slices are fetched while this level computes;
+      // the last buffer serves the overlap exchange first and is refilled after it
+      lds_barrier();
       if (next_ok) {
 #pragma unroll
-        for (int s = 0; s < NBUF; ++s) stage_slice<T, K>(sbuf + s * SLICE, r, s, vz + 1, X0, Y0, n, tid);
+        for (int s = 0; s < NBUF - 1; ++s) stage_slice<T, K>(buf(s), r, s, vz + 1, X0, Y0, n, tid);
       }
       // (2) fast diagonalization in registers
       contract_axis<2, true>(w, Seo);
@@ -354,9 +398,9 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
 #pragma unroll
           for (int ax = 0; ax < M; ++ax) w[az][ay][ax] = T(0);
       if (next_ok) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
-        for (int s = 0; s < NBUF; ++s) stage_slice<T, K>(sbuf + s * SLICE, r, s, vz + 1, X0, Y0, n, tid);
+        for (int s = 0; s < NBUF - 1; ++s) stage_slice<T, K>(buf(s), r, s, vz + 1, X0, Y0, n, tid);
       }
     }
 
@@ -380,28 +424,28 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
 #pragma unroll
         for (int i = 0; i < K; ++i) {
           T lo = T(0);
-          if (i < k) {
-            lo = __shfl_up(w[az][b][k - 1 + i], 1);
-            if (lane == 0) lo = T(0);   // patch vx-1 is not in this wavefront
-          }
+          if (i < k) lo = lane_shift_up(w[az][b][k - 1 + i]);   // lane 0: patch vx-1 is not in this wavefront
           if (i == 0) X[b][i] = lo;
           else if (i < k) X[b][i] = lo + w[az][b][i - 1];
           else X[b][i] = w[az][b][k - 1];
         }
       }
-      __syncthreads();   // the previous plane's readers are done
+      // planes alternate between two exchange buffers, so one barrier per plane
+      // suffices: a buffer is rewritten two planes later, after every reader
+      // has passed the barrier of the plane in between
+      T* xb = (az & 1) ? buf(NBUF - 1) : xch;
 #pragma unroll
       for (int j = 0; j < k; ++j)
 #pragma unroll
-        for (int i = 0; i < K; ++i) xch[(j * K + i) * (64 * WY) + tid] = X[k - 1 + j][i];
-      __syncthreads();
+        for (int i = 0; i < K; ++i) xb[(j * K + i) * (64 * WY) + tid] = X[k - 1 + j][i];
+      lds_barrier();
       T Y[K][K];
 #pragma unroll
       for (int j = 0; j < K; ++j)
 #pragma unroll
         for (int i = 0; i < K; ++i) {
           T lo = T(0);
-          if (j < k && wy >= 1) lo = xch[(j * K + i) * (64 * WY) + tid - 64];
+          if (j < k && wy >= 1) lo = xb[(j * K + i) * (64 * WY) + tid - 64];
           if (j == 0) Y[j][i] = lo;
           else if (j < k) Y[j][i] = lo + X[j - 1][i];
           else Y[j][i] = X[k - 1][i];
@@ -435,6 +479,11 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
 #pragma unroll
           for (int i = 0; i < K; ++i) out_hi[(az - k + 1) * K2 + j * K + i] = Y[j][i];
       }
+    }
+    // the exchange is done with the last slice buffer: refill it for the next level
+    if (next_ok) {
+      lds_barrier();
+      stage_slice<T, K>(buf(NBUF - 1), r, NBUF - 1, vz + 1, X0, Y0, n, tid);
     }
   }
   __builtin_amdgcn_s_waitcnt(0);
