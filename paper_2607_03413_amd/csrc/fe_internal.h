@@ -151,6 +151,12 @@ fe_status launch_gather(const fe_problem* p, const void* xg, void* xc, fe_dtype 
 fe_status launch_assemble(const fe_problem* p, const void* yc, void* yg, fe_dtype dt, hipStream_t s);
 fe_status launch_dss(const fe_problem* p, int level, void* v, int averaging, fe_dtype dt, hipStream_t s);
 fe_status launch_apply(const fe_problem* p, int level, const void* x, void* y, fe_dtype dt, hipStream_t s);
+// y = alpha A x + beta b (b may be null: y = alpha A x; b may alias y)
+fe_status launch_apply_ep(const fe_problem* p, int level, const void* x, void* y, double alpha, double beta,
+                          const void* b, fe_dtype dt, hipStream_t s);
+// Chebyshev step on cell-wise vectors: w = a v + c w (v may alias w); e = w (e_zero) or e + w
+fe_status launch_cheb_update(int64_t n, double a, const void* v, double c, void* w, void* e, int e_zero,
+                             fe_dtype dt, hipStream_t s);
 fe_status launch_patch_inverse(const fe_problem* p, int level, const void* r, void* z, void* scratch,
                                fe_dtype dt, int factors, hipStream_t s);
 size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt);
@@ -181,7 +187,8 @@ fe_status launch_diag_cartesian(const fe_problem* p, int level, void* d, fe_dtyp
 fe_status launch_diag_general(const fe_problem* p, int level, void* d, fe_dtype dt, hipStream_t s);
 fe_status launch_rhs_cartesian(const fe_problem* p, void* b, hipStream_t s);
 fe_status launch_rhs_general(const fe_problem* p, void* b, hipStream_t s);
-fe_status launch_apply_general(const fe_problem* p, int level, const void* x, void* y, fe_dtype dt, hipStream_t s);
+fe_status launch_apply_general(const fe_problem* p, int level, const void* x, void* y, double alpha, double beta,
+                               const void* b, fe_dtype dt, hipStream_t s);
 fe_status finish_reduction(const fe_problem* p, int nparts, double* dev_out, hipStream_t s);
 // deformed geometry setup (metric per level) and per-patch factors
 fe_status setup_geometry(fe_problem* p, hipStream_t s);

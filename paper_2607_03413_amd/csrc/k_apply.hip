@@ -16,9 +16,10 @@
 namespace fe {
 
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_apply_cart3(const T* __restrict__ x, T* __restrict__ y,
+__global__ void __launch_bounds__(256) k_apply_cart3(const T* __restrict__ x, T* y,
                                                      const T* __restrict__ Bm, const T* __restrict__ Dm,
-                                                     T scale, int n, int64_t n_cells, int dirichlet) {
+                                                     T scale, int n, int64_t n_cells, int dirichlet, T alpha,
+                                                     T beta, const T* bsrc) {
   constexpr int TPC = K * K;
   constexpr int CPB = 256 / TPC;
   constexpr int RS = K + 1;
@@ -103,22 +104,27 @@ __global__ void __launch_bounds__(256) k_apply_cart3(const T* __restrict__ x, T*
   for (int ix = 0; ix < K; ++ix) la[p1 * PS + p0 * RS + ix] = a[ix] * scale;
   __syncthreads();
 
-  // store through the z-pencil orientation (ix = p0, iy = p1)
+  // store through the z-pencil orientation (ix = p0, iy = p1), with the
+  // epilogue y = alpha A x + beta bsrc (read before y is written: bsrc may alias y)
   if (active) {
-    T* yc = y + cell * (K * K * K) + p0 + K * p1;
+    const int64_t off = cell * (K * K * K) + p0 + K * p1;
+    T* yc = y + off;
 #pragma unroll
     for (int iz = 0; iz < K; ++iz) {
       T val = la[iz * PS + p1 * RS + p0];
       if (zmask & (1u << iz)) val = T(0);
+      val *= alpha;
+      if (bsrc) val += beta * bsrc[off + iz * K * K];
       yc[iz * K * K] = val;
     }
   }
 }
 
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_apply_cart2(const T* __restrict__ x, T* __restrict__ y,
+__global__ void __launch_bounds__(256) k_apply_cart2(const T* __restrict__ x, T* y,
                                                      const T* __restrict__ Bm, const T* __restrict__ Dm,
-                                                     T scale, int n, int64_t n_cells, int dirichlet) {
+                                                     T scale, int n, int64_t n_cells, int dirichlet, T alpha,
+                                                     T beta, const T* bsrc) {
   constexpr int TPC = K;
   constexpr int CPB = 256 / TPC;
   constexpr int RS = K + 1;
@@ -170,9 +176,15 @@ __global__ void __launch_bounds__(256) k_apply_cart2(const T* __restrict__ x, T*
   for (int ix = 0; ix < K; ++ix) la[p * RS + ix] = a[ix] * scale;
   __syncthreads();
   if (active) {
-    T* yc = y + cell * (K * K) + p;
+    const int64_t off = cell * (K * K) + p;
+    T* yc = y + off;
 #pragma unroll
-    for (int iy = 0; iy < K; ++iy) yc[iy * K] = (ymask & (1u << iy)) ? T(0) : la[iy * RS + p];
+    for (int iy = 0; iy < K; ++iy) {
+      T val = (ymask & (1u << iy)) ? T(0) : la[iy * RS + p];
+      val *= alpha;
+      if (bsrc) val += beta * bsrc[off + iy * K];
+      yc[iy * K] = val;
+    }
   }
 }
 
@@ -197,8 +209,8 @@ __global__ void k_diag_cart(T* __restrict__ d, const T* __restrict__ Bm, const T
 }
 
 template <typename T, int K>
-static fe_status apply_typed(const fe_problem* p, const Level& L, const T* x, T* y, const T* coef,
-                             hipStream_t s) {
+static fe_status apply_typed(const fe_problem* p, const Level& L, const T* x, T* y, const T* coef, T alpha,
+                             T beta, const T* b, hipStream_t s) {
   const T* Bm = coef + p->co.off_B;
   const T* Dm = coef + p->co.off_D;
   const T scale = (T)(p->dim == 3 ? L.h : 1.0);
@@ -207,13 +219,13 @@ static fe_status apply_typed(const fe_problem* p, const Level& L, const T* x, T*
     const int64_t nb = (L.n_cells + CPB - 1) / CPB;
     ProfScope ps("apply", s);
     hipLaunchKernelGGL((k_apply_cart3<T, K>), dim3((unsigned)nb), dim3(CPB * K * K), 0, s, x, y, Bm, Dm,
-                       scale, L.n, L.n_cells, p->bc);
+                       scale, L.n, L.n_cells, p->bc, alpha, beta, b);
   } else {
     constexpr int CPB = 256 / K;
     const int64_t nb = (L.n_cells + CPB - 1) / CPB;
     ProfScope ps("apply", s);
     hipLaunchKernelGGL((k_apply_cart2<T, K>), dim3((unsigned)nb), dim3(CPB * K), 0, s, x, y, Bm, Dm,
-                       scale, L.n, L.n_cells, p->bc);
+                       scale, L.n, L.n_cells, p->bc, alpha, beta, b);
   }
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
@@ -229,18 +241,22 @@ static fe_status diag_typed(const fe_problem* p, const Level& L, T* d, const T* 
   return FE_OK;
 }
 
-fe_status launch_apply_general(const fe_problem* p, int level, const void* x, void* y, fe_dtype dt,
-                               hipStream_t s);
-
 fe_status launch_apply(const fe_problem* p, int level, const void* x, void* y, fe_dtype dt, hipStream_t s) {
-  if (p->desc.geometry == FE_GEOM_DEFORMED) return launch_apply_general(p, level, x, y, dt, s);
+  return launch_apply_ep(p, level, x, y, 1.0, 0.0, nullptr, dt, s);
+}
+
+fe_status launch_apply_ep(const fe_problem* p, int level, const void* x, void* y, double alpha, double beta,
+                          const void* b, fe_dtype dt, hipStream_t s) {
+  if (p->desc.geometry == FE_GEOM_DEFORMED) return launch_apply_general(p, level, x, y, alpha, beta, b, dt, s);
   const Level& L = level_of(p, level);
   if (dt == FE_F64) {
     FE_DISPATCH_K(p->K, return (apply_typed<double, KK>(p, L, (const double*)x, (double*)y,
-                                                        p->coef64.as<double>(), s)));
+                                                        p->coef64.as<double>(), alpha, beta, (const double*)b,
+                                                        s)));
   } else {
     FE_DISPATCH_K(p->K, return (apply_typed<float, KK>(p, L, (const float*)x, (float*)y,
-                                                       p->coef32.as<float>(), s)));
+                                                       p->coef32.as<float>(), (float)alpha, (float)beta,
+                                                       (const float*)b, s)));
   }
 }
 

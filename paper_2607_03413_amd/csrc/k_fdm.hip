@@ -372,43 +372,31 @@ __device__ __forceinline__ AxisPatches axis_patches(int g, int n) {
   return a;
 }
 
-template <typename T, int K, int DIM>
-__global__ void __launch_bounds__(256) k_fdm_sum(const T* __restrict__ W, T* __restrict__ z, int n,
-                                                 int64_t len) {
+// Kernel (2), 2D: one thread per cell-wise entry sums the patch-major
+// solutions of the (at most 4) patches containing its node, in ascending
+// vertex order (y, then x), so all copies receive identical values.
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_fdm_sum2(const T* __restrict__ W, T* __restrict__ z, int n,
+                                                  int64_t len) {
   constexpr int k = K - 1;
   constexpr int M = 2 * k - 1;
-  constexpr int NL = DIM == 3 ? K * K * K : K * K;
-  constexpr int MP = DIM == 3 ? M * M * M : M * M;
+  constexpr int NL = K * K;
+  constexpr int MP = M * M;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= len) return;
   const int64_t cell = e / NL;
   const int loc = (int)(e - cell * NL);
-  const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
-  const int cx = (int)(cell % n);
-  const int64_t t = cell / n;
+  const int ix = loc % K, iy = loc / K;
+  const int cx = (int)(cell % n), cy = (int)(cell / n);
   const int nv = n - 1;
+  const AxisPatches px = axis_patches<K>(k * cx + ix, n);
+  const AxisPatches py = axis_patches<K>(k * cy + iy, n);
   T s = T(0);
-  if (DIM == 3) {
-    const int cy = (int)(t % n), cz = (int)(t / n);
-    const AxisPatches px = axis_patches<K>(k * cx + ix, n);
-    const AxisPatches py = axis_patches<K>(k * cy + iy, n);
-    const AxisPatches pz = axis_patches<K>(k * cz + iz, n);
-    for (int a = 0; a < pz.cnt; ++a)
-      for (int b = 0; b < py.cnt; ++b)
-        for (int c = 0; c < px.cnt; ++c) {
-          const int64_t pid = (px.v[c] - 1) + (int64_t)nv * ((py.v[b] - 1) + (int64_t)nv * (pz.v[a] - 1));
-          s += W[pid * MP + px.o[c] + M * (py.o[b] + M * pz.o[a])];
-        }
-  } else {
-    const int cy = (int)t;
-    const AxisPatches px = axis_patches<K>(k * cx + ix, n);
-    const AxisPatches py = axis_patches<K>(k * cy + iy, n);
-    for (int b = 0; b < py.cnt; ++b)
-      for (int c = 0; c < px.cnt; ++c) {
-        const int64_t pid = (px.v[c] - 1) + (int64_t)nv * (py.v[b] - 1);
-        s += W[pid * MP + px.o[c] + M * py.o[b]];
-      }
-  }
+  for (int b = 0; b < py.cnt; ++b)
+    for (int c = 0; c < px.cnt; ++c) {
+      const int64_t pid = (px.v[c] - 1) + (int64_t)nv * (py.v[b] - 1);
+      s += W[pid * MP + px.o[c] + M * py.o[b]];
+    }
   z[e] = s;
 }
 
@@ -521,7 +509,7 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
       FE_HIP_CHECK(hipGetLastError());
     }
     ProfScope ps2("fdm_sum", s);
-    hipLaunchKernelGGL((k_fdm_sum<T, K, 2>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
+    hipLaunchKernelGGL((k_fdm_sum2<T, K>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
                        L.len);
   }
   FE_HIP_CHECK(hipGetLastError());

@@ -173,10 +173,10 @@ __global__ void k_convert_metric(const double* __restrict__ a, T* __restrict__ b
 // K^2 threads per cell; forward: z (PHI, DPHI), y (3), x (3) contractions;
 // metric; backward: x (3), y (2 accumulating into 2), z (2 into 1).
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x, T* __restrict__ y,
+__global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x, T* y,
                                                         const T* __restrict__ G, const T* __restrict__ PHI,
                                                         const T* __restrict__ DPHI, int n, int64_t n_cells,
-                                                        int dirichlet) {
+                                                        int dirichlet, T alpha, T beta, const T* bsrc) {
   constexpr int TPC = K * K;
   constexpr int CPB = 256 / TPC;
   constexpr int RS = K + 1, PS = K * RS, CS = K * PS;
@@ -296,9 +296,16 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
     pencil_mtv<T, K>(PHI, v, t1);
     pencil_mtv<T, K>(DPHI, w, t2);
     if (active) {
-      T* yc = y + cell * K3 + p0 + K * p1;
+      // epilogue y = alpha A x + beta bsrc (read before y is written: bsrc may alias y)
+      const int64_t off = cell * K3 + p0 + K * p1;
+      T* yc = y + off;
 #pragma unroll
-      for (int iz = 0; iz < K; ++iz) yc[iz * K * K] = (zmask & (1u << iz)) ? T(0) : t1[iz] + t2[iz];
+      for (int iz = 0; iz < K; ++iz) {
+        T val = (zmask & (1u << iz)) ? T(0) : t1[iz] + t2[iz];
+        val *= alpha;
+        if (bsrc) val += beta * bsrc[off + iz * K * K];
+        yc[iz * K * K] = val;
+      }
     }
   }
 }
@@ -454,24 +461,27 @@ fe_status setup_geometry(fe_problem* p, hipStream_t s) {
 
 template <typename T, int K>
 static fe_status apply_general_typed(const fe_problem* p, const Level& L, const T* x, T* y, const T* G,
-                                     const T* tab, hipStream_t s) {
+                                     const T* tab, T alpha, T beta, const T* b, hipStream_t s) {
   constexpr int CPB = 256 / (K * K);
   const unsigned nb = (unsigned)((L.n_cells + CPB - 1) / CPB);
   ProfScope ps("apply_general", s);
   hipLaunchKernelGGL((k_apply_general3<T, K>), dim3(nb), dim3(CPB * K * K), 0, s, x, y, G, tab, tab + K * K, L.n,
-                     L.n_cells, p->bc);
+                     L.n_cells, p->bc, alpha, beta, b);
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
 }
 
-fe_status launch_apply_general(const fe_problem* p, int level, const void* x, void* y, fe_dtype dt, hipStream_t s) {
+fe_status launch_apply_general(const fe_problem* p, int level, const void* x, void* y, double alpha, double beta,
+                               const void* b, fe_dtype dt, hipStream_t s) {
   const Level& L = level_of(p, level);
   if (dt == FE_F64) {
     FE_DISPATCH_K(p->K, return (apply_general_typed<double, KK>(p, L, (const double*)x, (double*)y,
-                                                                L.metric64.as<double>(), p->geo_tab64.as<double>(), s)));
+                                                                L.metric64.as<double>(), p->geo_tab64.as<double>(),
+                                                                alpha, beta, (const double*)b, s)));
   }
   FE_DISPATCH_K(p->K, return (apply_general_typed<float, KK>(p, L, (const float*)x, (float*)y,
-                                                             L.metric32.as<float>(), p->geo_tab32.as<float>(), s)));
+                                                             L.metric32.as<float>(), p->geo_tab32.as<float>(),
+                                                             (float)alpha, (float)beta, (const float*)b, s)));
 }
 
 template <int K>

@@ -212,6 +212,17 @@ __global__ void __launch_bounds__(256) k_axpby(int64_t n, T a, const T* __restri
   if (e < n) y[e] = b == T(0) ? a * x[e] : fma(a, x[e], b * y[e]);
 }
 
+// Chebyshev step: w = a v + c w (v may alias w), then e = w or e += w.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cheb_update(int64_t n, T a, const T* v, T c, T* w, T* __restrict__ e,
+                                                     int e_zero) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T wn = c == T(0) ? a * v[i] : fma(a, v[i], c * w[i]);
+  w[i] = wn;
+  e[i] = e_zero ? wn : e[i] + wn;
+}
+
 template <typename S, typename D>
 __global__ void __launch_bounds__(256) k_cast(int64_t n, const S* __restrict__ x, D* __restrict__ y) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -436,6 +447,19 @@ fe_status launch_axpby(int64_t n, double a, const void* x, double b, void* y, fe
     hipLaunchKernelGGL(k_axpby<double>, dim3(nb), dim3(256), 0, s, n, a, (const double*)x, b, (double*)y);
   else
     hipLaunchKernelGGL(k_axpby<float>, dim3(nb), dim3(256), 0, s, n, (float)a, (const float*)x, (float)b, (float*)y);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status launch_cheb_update(int64_t n, double a, const void* v, double c, void* w, void* e, int e_zero,
+                             fe_dtype dt, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (dt == FE_F64)
+    hipLaunchKernelGGL(k_cheb_update<double>, dim3(nb), dim3(256), 0, s, n, a, (const double*)v, c, (double*)w,
+                       (double*)e, e_zero);
+  else
+    hipLaunchKernelGGL(k_cheb_update<float>, dim3(nb), dim3(256), 0, s, n, (float)a, (const float*)v, (float)c,
+                       (float*)w, (float*)e, e_zero);
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
 }

@@ -204,26 +204,17 @@ static fe_status cheb_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe_d
   for (int sw = 0; sw < sweeps; ++sw) {
     const bool z = u_zero && sw == 0;
     double rho = 1.0 / sigma;
-    // t = b - A e
-    if (z) {
-      FE_CHECK(launch_cast(n, b, dt, t, dt, s));
-    } else {
-      FE_CHECK(launch_apply(p, l, e, v, dt, s));
-      FE_CHECK(launch_cast(n, b, dt, t, dt, s));
-      FE_CHECK(launch_axpby(n, -1.0, v, 1.0, t, dt, s));
-    }
+    // t = b - A e (the residual fused into the operator's store)
+    if (z) FE_CHECK(launch_cast(n, b, dt, t, dt, s));
+    else FE_CHECK(launch_apply_ep(p, l, e, t, -1.0, 1.0, b, dt, s));
     // w = P t / theta; e += w
     FE_CHECK(patch_apply(p, l, t, w, dt, o.factors, s));
-    FE_CHECK(launch_axpby(n, 1.0 / theta, w, 0.0, w, dt, s));
-    if (z) FE_CHECK(launch_cast(n, w, dt, e, dt, s));
-    else FE_CHECK(launch_axpby(n, 1.0, w, 1.0, e, dt, s));
+    FE_CHECK(launch_cheb_update(n, 1.0 / theta, w, 0.0, w, e, z ? 1 : 0, dt, s));
     for (int it = 1; it < o.cheb_degree; ++it) {
-      FE_CHECK(launch_apply(p, l, w, v, dt, s));          // v = A w
-      FE_CHECK(launch_axpby(n, -1.0, v, 1.0, t, dt, s));  // t -= A w
+      FE_CHECK(launch_apply_ep(p, l, w, t, -1.0, 1.0, t, dt, s));   // t -= A w
       const double rho_new = 1.0 / (2.0 * sigma - rho);
-      FE_CHECK(patch_apply(p, l, t, v, dt, o.factors, s));  // v = P t (primal)
-      FE_CHECK(launch_axpby(n, 2.0 * rho_new / delta, v, rho_new * rho, w, dt, s));
-      FE_CHECK(launch_axpby(n, 1.0, w, 1.0, e, dt, s));
+      FE_CHECK(patch_apply(p, l, t, v, dt, o.factors, s));         // v = P t (primal)
+      FE_CHECK(launch_cheb_update(n, 2.0 * rho_new / delta, v, rho_new * rho, w, e, 0, dt, s));
       rho = rho_new;
     }
   }
