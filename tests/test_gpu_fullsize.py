@@ -145,6 +145,37 @@ def test_patch_inverse_full_size(gpu_lib, k, n):
     P.close()
 
 
+@pytest.mark.parametrize("n", [2, 33, 34, 40])
+def test_patch_inverse_tile_seams(gpu_lib, n):
+    """Q3 at sizes that place the x-tile, y-tile and z-chunk seams of the
+    blocked kernels differently (one x-tile; 32 patches in a row; a last x-tile
+    that mostly overlaps the first; a partial last tile): sampled cells on and
+    next to every seam against the oracle, and bit-identical copies everywhere."""
+    fe = gpu_lib
+    k = 3
+    m = StructuredMesh(3, k, n)
+    r = uniform(m.n_cellwise, seed=206)
+    g = rng(207)
+    xs = sorted({c for c in (0, 1, 29, 30, 31, 32, 33, n - 2, n - 1) if 0 <= c < n})
+    ys = sorted({c for c in (0, 6, 7, 8, 13, 14, n - 2, n - 1) if 0 <= c < n})
+    cells = {x + n * (y + n * int(g.integers(0, n))) for x in xs for y in ys}
+    cells |= {x + n * (y + n * z) for x in xs for y in (0, n - 1) for z in (0, n - 1)}
+    cells = np.array(sorted(cells), dtype=np.int64)
+    expect = patch_inverse_at_cells(k, n, m.assemble(r), cells)
+    P = fe.Problem(3, k, n, bc=1)
+    idx = m.global_index_map().ravel()
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        z = P.cellvec(dtype)
+        P.patch_inverse(dev(r, dtype), z)
+        zh = host(z)
+        got = zh.reshape(m.n_cells, -1)[cells]
+        assert relerr(got, expect) < tol, (dtype, relerr(got, expect))
+        first = np.full(m.n_global, np.nan)
+        first[idx[::-1]] = zh[::-1]
+        assert np.array_equal(zh, first[idx])
+    P.close()
+
+
 @pytest.mark.parametrize("k,n,with_coef", [(3, 48, True), (7, 64, False)])
 def test_general_apply_full_size(gpu_lib, k, n, with_coef):
     """Q3 48^3 with the coefficient field of the benchmark; Q7 64^3 deformed with
