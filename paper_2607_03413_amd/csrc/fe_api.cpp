@@ -247,7 +247,7 @@ fe_status fe_problem_create(const fe_problem_desc* desc, void* stream, fe_proble
       for (int jo = 0; jo < no; ++jo) lm[ne + jo] = p->lam[odd[jo]];
       seo.insert(seo.end(), lm.begin(), lm.end());
       p->co.off_Seo = put(seo);
-      if (k <= 3) {
+      {
         // inverse eigenvalue sums in that mode order, scaled by h^{2-d} per level
         std::vector<double> il;
         for (const Level& L : p->levels) {

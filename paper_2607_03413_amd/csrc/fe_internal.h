@@ -72,9 +72,9 @@ struct Coef1D {
   int off_S = 0, off_lam = 0;   // Cartesian patch eigen-data, scaled for h = 1
   // 3D Cartesian, k >= 2: even/odd halves of the 1D patch eigenvectors,
   // SE[(k)][k] then SO[(k-1)][k-1], then the M eigenvalues in that mode order
-  // (evens first); for k = 2, 3 (fused patch inverse) also per level l the M^3
-  // entries h_l^{-1} / (lam_x + lam_y + lam_z) in that mode order, index
-  // (mz*M + my)*M + mx, at off_il + l*M^3 (-1: not built)
+  // (evens first); then per level l the M^3 entries h_l^{-1} / (lam_x + lam_y
+  // + lam_z) in that mode order, index (mz*M + my)*M + mx, at off_il + l*M^3
+  // (-1: not built)
   int off_Seo = -1, off_il = -1;
 };
 

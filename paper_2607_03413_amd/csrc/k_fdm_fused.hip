@@ -435,8 +435,9 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
         }
       }
       // planes alternate between two exchange buffers, so one barrier per plane
-      // suffices: a buffer is rewritten two planes later, after every reader
-      // has passed the barrier of the plane in between
+      // suffices within a level: a buffer is rewritten two planes later, after
+      // every reader has passed the barrier of the plane in between (across
+      // levels, see the barrier at the end of the level)
       T* xb = (az & 1) ? buf(NBUF - 1) : xch;
 #pragma unroll
       for (int j = 0; j < k; ++j)
@@ -484,11 +485,13 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
           for (int i = 0; i < K; ++i) out_hi[(az - k + 1) * K2 + j * K + i] = Y[j][i];
       }
     }
-    // the exchange is done with the last slice buffer: refill it for the next level
-    if (next_ok) {
-      lds_barrier();
-      stage_slice<T, K>(buf(NBUF - 1), r, NBUF - 1, vz + 1, X0, Y0, n, tid);
-    }
+    // Every wavefront has read the exchange data of this level's last plane
+    // before the next level writes it: the last plane (M-1, even) and the next
+    // level's first plane (0, even) use the same buffer, and a level without a
+    // patch (vz = n) stages nothing, so no other barrier separates them.  Then
+    // the last slice buffer is refilled for the next level.
+    lds_barrier();
+    if (next_ok) stage_slice<T, K>(buf(NBUF - 1), r, NBUF - 1, vz + 1, X0, Y0, n, tid);
   }
   __builtin_amdgcn_s_waitcnt(0);
 }

@@ -125,10 +125,12 @@ __device__ __forceinline__ AxisCopies wave_axis_copies(int a) {
 }
 
 // eig (PER_PATCH): per patch S_x, S_y, S_z (M x M), l_x, l_y, l_z (M);
-// otherwise (EO) the even/odd halves of the Cartesian S and the eigenvalues.
+// otherwise (EO) the even/odd halves of the Cartesian S and the eigenvalues,
+// and il the level's table of scale / (l_x + l_y + l_z) in the same mode order.
 template <typename T, int K, bool PER_PATCH>
 __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r, T* __restrict__ W,
-                                                        const T* __restrict__ eig, T scale, int n) {
+                                                        const T* __restrict__ eig, const T* __restrict__ il,
+                                                        T scale, int n) {
   using P = WavePatch<K>;
   constexpr int k = P::k, M = P::M, M2 = P::M2, M3 = P::M3, ROUNDS = P::ROUNDS;
   constexpr int K3 = K * K * K;
@@ -215,9 +217,14 @@ __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r,
 #pragma unroll
       for (int a = 0; a < M; ++a) v[a] = t[z * M2 + y * M + a];
       line_apply<T, M, EO, true>(Sx, v, w);
-      const T lyz = ly[y] + lz[z];
+      if (PER_PATCH) {
+        const T lyz = ly[y] + lz[z];
 #pragma unroll
-      for (int a = 0; a < M; ++a) w[a] *= scale * recip(lx[a] + lyz);
+        for (int a = 0; a < M; ++a) w[a] *= scale * recip(lx[a] + lyz);
+      } else {
+#pragma unroll
+        for (int a = 0; a < M; ++a) w[a] *= il[l * M + a];
+      }
       line_apply<T, M, EO, false>(Sx, w, v);
 #pragma unroll
       for (int a = 0; a < M; ++a) t[z * M2 + y * M + a] = v[a];
@@ -261,15 +268,17 @@ bool patch_wave_supported(const fe_problem* p, bool per_patch) {
 }
 
 template <typename T, int K>
-static fe_status patch_wave_typed(const Level& L, const T* r, T* W, const T* eig, bool per_patch, T scale,
-                                  hipStream_t s) {
+static fe_status patch_wave_typed(const Level& L, const T* r, T* W, const T* eig, const T* il, bool per_patch,
+                                  T scale, hipStream_t s) {
   const int64_t nv = L.n - 1, np = nv * nv * nv;
   if (np == 0) return FE_OK;
   ProfScope ps("fdm_patch", s);
   if (per_patch)
-    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, true>), dim3((unsigned)np), dim3(64), 0, s, r, W, eig, scale, L.n);
+    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, true>), dim3((unsigned)np), dim3(64), 0, s, r, W, eig, il, scale,
+                       L.n);
   else
-    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, false>), dim3((unsigned)np), dim3(64), 0, s, r, W, eig, scale, L.n);
+    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, false>), dim3((unsigned)np), dim3(64), 0, s, r, W, eig, il, scale,
+                       L.n);
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
 }
@@ -277,6 +286,9 @@ static fe_status patch_wave_typed(const Level& L, const T* r, T* W, const T* eig
 // eig: per-patch eigen-data (per_patch) or null (the Cartesian even/odd table is used)
 fe_status launch_patch_wave(const fe_problem* p, const Level& L, const void* r, void* W, const void* eig,
                             bool per_patch, double scale, fe_dtype dt, hipStream_t s) {
+  if (!per_patch && p->co.off_il < 0) return fail(FE_EUNSUPPORTED, "wave patch inverse: no eigenvalue table");
+  const int64_t M = 2 * p->k - 1;
+  const int64_t il_off = per_patch ? 0 : p->co.off_il + (int64_t)(&L - p->levels.data()) * M * M * M;
   switch (p->K) {
 #define FE_WAVE_CASE(KV)                                                                                   \
   case KV:                                                                                                 \
@@ -284,10 +296,10 @@ fe_status launch_patch_wave(const fe_problem* p, const Level& L, const void* r, 
       return patch_wave_typed<double, KV>(L, (const double*)r, (double*)W,                                 \
                                           per_patch ? (const double*)eig                                   \
                                                     : p->coef64.as<double>() + p->co.off_Seo,              \
-                                          per_patch, scale, s);                                            \
+                                          p->coef64.as<double>() + il_off, per_patch, scale, s);           \
     return patch_wave_typed<float, KV>(L, (const float*)r, (float*)W,                                      \
                                        per_patch ? (const float*)eig : p->coef32.as<float>() + p->co.off_Seo, \
-                                       per_patch, (float)scale, s);
+                                       p->coef32.as<float>() + il_off, per_patch, (float)scale, s);
     FE_WAVE_CASE(5)
     FE_WAVE_CASE(6)
     FE_WAVE_CASE(7)
