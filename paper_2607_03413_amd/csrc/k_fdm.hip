@@ -400,39 +400,34 @@ __global__ void __launch_bounds__(256) k_fdm_sum2(const T* __restrict__ W, T* __
   z[e] = s;
 }
 
-// Kernel (2), 3D, patch-major solutions (k >= 4): one thread per cell-wise
-// entry, a fixed 2 x 2 x 2 set of candidate patches per entry so that lanes do
-// not diverge.  Along each axis the node g = k c + i lies strictly inside
+// Kernel (2), 3D, patch-major solutions (k >= 4): one block per cell, one
+// thread per cell-wise entry, a fixed 2 x 2 x 2 set of candidate patches per
+// entry so that lanes do not diverge.  Along each axis the node g = k c + i lies strictly inside
 // patch c (offset k-1+i) when i < k and inside patch c+1 (offset i-1) when
 // i > 0; candidates outside 1..n-1 or not containing the node contribute 0.
 // The sum runs over (z, y, x) patch candidates in ascending vertex order,
 // which depends only on the node: all copies receive identical values.
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n,
-                                                     int64_t len) {
+__global__ void __launch_bounds__(K * K * K) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n) {
   constexpr int k = K - 1;
   constexpr int M = 2 * k - 1;
   constexpr int MP = M * M * M;
   constexpr int NL = K * K * K;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= len) return;
-  const int64_t cell = e / NL;
-  const int loc = (int)(e - cell * NL);
+  // one block per cell: the cell and its candidate patches are block-uniform
+  // (scalar arithmetic); each thread owns one node of the cell
+  const int cell = blockIdx.x;
+  const int cx = cell % n, cy = (cell / n) % n, cz = cell / (n * n);
+  const int loc = threadIdx.x;
   const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
-  const int cx = (int)(cell % n);
-  const int64_t t = cell / n;
-  const int cy = (int)(t % n), cz = (int)(t / n);
   const int nv = n - 1;
   // candidate c = 0: vertex = cell (offset k-1+i), c = 1: vertex = cell+1 (offset i-1)
   const int c3[3] = {cx, cy, cz}, i3[3] = {ix, iy, iz};
-  int vtx[3][2], off[3][2];
+  int off[3][2];
   bool ok[3][2];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    vtx[a][0] = c3[a];
     off[a][0] = k - 1 + i3[a];
     ok[a][0] = i3[a] < k && c3[a] >= 1;
-    vtx[a][1] = c3[a] + 1;
     off[a][1] = i3[a] - 1;
     ok[a][1] = i3[a] > 0 && c3[a] + 1 <= nv;
   }
@@ -444,11 +439,11 @@ __global__ void __launch_bounds__(256) k_fdm_sum_pm3(const T* __restrict__ W, T*
 #pragma unroll
       for (int bx = 0; bx < 2; ++bx) {
         const bool use = ok[2][bz] && ok[1][by] && ok[0][bx];
-        const int64_t pid = (vtx[0][bx] - 1) + (int64_t)nv * ((vtx[1][by] - 1) + (int64_t)nv * (vtx[2][bz] - 1));
+        const int64_t pid = (cx + bx - 1) + (int64_t)nv * ((cy + by - 1) + (int64_t)nv * (cz + bz - 1));
         const int o = off[0][bx] + M * (off[1][by] + M * off[2][bz]);
         if (use) s += W[pid * MP + o];   // masked load: no access for absent patches
       }
-  z[e] = s;
+  z[(int64_t)cell * NL + loc] = s;
 }
 
 bool fused_patch_supported(const fe_problem* p, bool per_patch);
@@ -491,8 +486,7 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
     }
     ProfScope ps2("fdm_sum", s);
     if (patch_wave_supported(p, per_patch))   // patch-major solutions
-      hipLaunchKernelGGL((k_fdm_sum_pm3<T, K>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z, L.n,
-                         L.len);
+      hipLaunchKernelGGL((k_fdm_sum_pm3<T, K>), dim3((unsigned)L.n_cells), dim3(K * K * K), 0, s, W, z, L.n);
     else                                      // slot-split solutions
       hipLaunchKernelGGL((k_fdm_sum_slots3<T, K>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z,
                          L.n, L.len);
