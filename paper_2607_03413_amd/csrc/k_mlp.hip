@@ -385,6 +385,15 @@ struct MlpWork {
 
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// The model changed: the learned patch factors of every level, and the
+// Chebyshev eigenvalue estimates taken with them, are out of date.
+static void invalidate_learned_factors(fe_problem* p) {
+  for (Level& L : p->levels) {
+    L.patch_eig_ready[2] = false;
+    if (L.lmax_key >= 0 && L.lmax_key / 1000 == 2) L.lmax_key = -1;
+  }
+}
+
 static fe_status mlp_forward(const float* P, const float* X, int nb, MlpWork& w, hipStream_t s) {
   const float *W1 = P, *b1 = W1 + kW1, *W2 = b1 + kHid, *b2 = W2 + kW2, *W3 = b2 + kHid, *b3 = W3 + kW3;
   hipLaunchKernelGGL(k_layer_fwd, dim3(nblk(nb * kHid)), dim3(256), 0, s, X, W1, b1, w.a1.as<float>(), nb, kIn, kHid, 1);
@@ -693,7 +702,7 @@ fe_status fe_mlp_set_params(fe_problem* p, const float* params, void* stream) {
   FE_HIP_CHECK(hipStreamSynchronize(s));
   p->mlp_ready = 1;
   p->mlp_step = 0;
-  for (Level& L : p->levels) L.patch_eig_ready[2] = false;
+  invalidate_learned_factors(p);
   return FE_OK;
 }
 
@@ -753,7 +762,7 @@ fe_status fe_mlp_adam_step(fe_problem* p, const float* grad, double lr, void* st
                      p->mlp_adam_m.as<float>(), p->mlp_adam_v.as<float>(), kParams, (float)lr,
                      (float)(1.0 - std::pow(0.9, t)), (float)(1.0 - std::pow(0.999, t)));
   FE_HIP_CHECK(hipGetLastError());
-  for (Level& L : p->levels) L.patch_eig_ready[2] = false;
+  invalidate_learned_factors(p);
   return FE_OK;
 }
 
@@ -806,7 +815,7 @@ fe_status fe_mlp_train(fe_problem* p, const float* X, const float* T, int n, int
     last = nbt ? ep_loss / nbt : 0.0;
   }
   FE_HIP_CHECK(hipGetLastError());
-  for (Level& L : p->levels) L.patch_eig_ready[2] = false;
+  invalidate_learned_factors(p);
   if (final_loss) *final_loss = last;
   return FE_OK;
 }

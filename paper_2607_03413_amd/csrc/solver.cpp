@@ -122,7 +122,18 @@ fe_status solver_setup(fe_problem* p, const fe_pcg_opts* o, hipStream_t s) {
   FE_CHECK(ensure_coarse_inverse(p, s));
   if (!p->solver) p->solver = new Solver();
   Solver& S = *p->solver;
-  if (S.ready && same_setup(S.opts, *o)) {
+  // the per-level data the options need (patch factors, Chebyshev bounds) can
+  // be invalidated between calls, e.g. when the factor model is retrained
+  bool levels_ready = true;
+  if (o->smoother == FE_SMOOTH_CHEB_FDM) {
+    const int key = o->factors * 1000 + 15;
+    for (size_t l = 1; l < p->levels.size(); ++l) {
+      const Level& L = p->levels[l];
+      if ((o->factors != 0 && !L.patch_eig_ready[o->factors]) || (o->cheb_lmax <= 0.0 && L.lmax_key != key))
+        levels_ready = false;
+    }
+  }
+  if (S.ready && levels_ready && same_setup(S.opts, *o)) {
     S.opts = *o;
     return FE_OK;
   }

@@ -130,3 +130,37 @@ def test_training_reduces_loss_and_learned_factors_help_pcg(gpu_lib):
     print("PCG iterations: averaged %d, learned %d, best fit %d" % (its[1], its[2], its[3]))
     assert its[2] <= its[1] + 1, its
     assert its[2] <= its[3] + 1, its
+
+
+def test_retrained_model_refreshes_learned_factors(gpu_lib):
+    """A solve with learned factors after the model changed uses factors of the
+    new model: the level factors and the Chebyshev bounds taken with them are
+    rebuilt, and the result equals that of a fresh problem with the same model."""
+    fe = gpu_lib
+    k = 2
+    Pt = problem(fe, k, 8, amp=0.1, seed=1000)
+    X, T = Pt.patch_features(), Pt.patch_fit_targets(sweeps=20)
+    Pt.close()
+    opts = fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1, factors=2,
+                           nu_pre=1, nu_post=1, tol=1e-10)
+    P = problem(fe, k, 8, amp=AMP, seed=2)
+    b = P.cellvec()
+    P.rhs_manufactured(b)
+    P.mlp_set_params(torch.as_tensor(init_params(20), dtype=torch.float32, device="cuda"))
+    P.mlp_train(X, T, epochs=5, batch=256, lr=2e-3, seed=5)
+    x = P.cellvec()
+    assert P.pcg_solve(b, x, opts)["converged"]
+    # retrain (same options in the next solve), then compare with a fresh problem holding the same model
+    P.mlp_train(X, T, epochs=10, batch=256, lr=2e-3, seed=6)
+    params = P.mlp_get_params().clone()
+    x1 = P.cellvec()
+    r1 = P.pcg_solve(b, x1, opts)
+    Q = problem(fe, k, 8, amp=AMP, seed=2)
+    Q.mlp_set_params(params)
+    x2 = Q.cellvec()
+    r2 = Q.pcg_solve(b, x2, opts)
+    assert r1["converged"] and r2["converged"]
+    assert r1["iters"] == r2["iters"], (r1["iters"], r2["iters"])
+    assert relerr(host(x1), host(x2)) < 1e-12
+    P.close()
+    Q.close()
