@@ -1,18 +1,21 @@
-// Vertex-patch fast-diagonalization inverse with one wavefront per patch
-// (3D, k >= 4: m = 2k-1 = 7..15, m^3 patch values in LDS).
+// Vertex-patch fast-diagonalization inverse with one block per patch and one
+// lane per pencil (3D, k >= 4: m = 2k-1 = 7..15, m^2 pencils of m values,
+// m^3 patch values in LDS; Q7: 169 pencils on three wavefronts).
 //
 // z = G sum_p R_p^T (S_x x S_y x S_z) (L_x + L_y + L_z)^{-1} (S_x x S_y x S_z)^T R_p G^T r
 // (vertex-patch smoother admissible by eq. precond_consistency, Sec. 2.1;
 // fast diagonalization of the separable patch operator).  The 1D factors
 // are uniform over a wavefront, so S and the eigenvalues are read through
 // the scalar cache and every FMA takes one operand from a scalar register:
-//   * lanes own pencils (lines of m values) of the patch, lane + 64 i;
+//   * lane l owns pencil l (a line of m values) of every pass, so a patch is
+//     spread over several wavefronts and each pass is one round; the LDS
+//     array of a patch limits how many patches a CU holds, not the lanes;
 //   * the residual is assembled per z-pencil straight from the cell-wise
 //     input (copies summed in cascade order: x pairs, then y, then z) and
 //     contracted with S_z^T in registers before it reaches LDS;
 //   * y: S_y^T; x: S_x^T, scaling by the inverse eigenvalue sums, S_x; y: S_y,
-//     each an in-place pass over LDS lines (no two lanes share a line, so a
-//     wavefront-level fence between the passes suffices);
+//     each an in-place pass over LDS lines (no two lanes share a line; a
+//     workgroup barrier separates the passes);
 //   * z: S_z in registers, and the patch solution is written patch-major
 //     (m^3 values per patch) for the summing pass.
 // With the exact Cartesian factors the mirror symmetry of the two-cell patch
@@ -29,16 +32,10 @@ struct WavePatch {
   static constexpr int M = 2 * k - 1;
   static constexpr int M2 = M * M;
   static constexpr int M3 = M2 * M;
-  static constexpr int ROUNDS = (M2 + 63) / 64;
+  static constexpr int THREADS = (M2 + 63) / 64 * 64;   // one lane per pencil, whole wavefronts
   static constexpr int C = k - 1;         // middle node
   static constexpr int NE = C + 1, NO = C;
 };
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // 1 / x: hardware reciprocal refined by Newton steps r <- r (2 - x r).
 __device__ __forceinline__ double recip(double x) {
@@ -128,11 +125,11 @@ __device__ __forceinline__ AxisCopies wave_axis_copies(int a) {
 // otherwise (EO) the even/odd halves of the Cartesian S and the eigenvalues,
 // and il the level's table of scale / (l_x + l_y + l_z) in the same mode order.
 template <typename T, int K, bool PER_PATCH>
-__global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r, T* __restrict__ W,
+__global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const T* __restrict__ r, T* __restrict__ W,
                                                         const T* __restrict__ eig, const T* __restrict__ il,
                                                         T scale, int n) {
   using P = WavePatch<K>;
-  constexpr int k = P::k, M = P::M, M2 = P::M2, M3 = P::M3, ROUNDS = P::ROUNDS;
+  constexpr int k = P::k, M = P::M, M2 = P::M2, M3 = P::M3;
   constexpr int K3 = K * K * K;
   constexpr bool EO = !PER_PATCH;
   __shared__ T t[M3];
@@ -159,9 +156,8 @@ __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r,
   const int64_t sy_cells = (int64_t)n * K3, sz_cells = (int64_t)n * n * K3;
 
   // (1) z-pencils (x, y): assemble, S_z^T, store
-#pragma unroll
-  for (int ro = 0; ro < ROUNDS; ++ro) {
-    const int l = lane + 64 * ro;
+  {
+    const int l = lane;
     if (l < M2) {
       const int x = l % M, y = l / M;
       const AxisCopies cx = wave_axis_copies<K>(x), cy = wave_axis_copies<K>(y);
@@ -191,11 +187,10 @@ __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r,
       for (int z = 0; z < M; ++z) t[z * M2 + y * M + x] = w[z];
     }
   }
-  wave_sync();
+  __syncthreads();
   // (2) y-pencils (x, z): S_y^T
-#pragma unroll
-  for (int ro = 0; ro < ROUNDS; ++ro) {
-    const int l = lane + 64 * ro;
+  {
+    const int l = lane;
     if (l < M2) {
       const int x = l % M, z = l / M;
       T v[M], w[M];
@@ -206,11 +201,10 @@ __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r,
       for (int a = 0; a < M; ++a) t[z * M2 + a * M + x] = w[a];
     }
   }
-  wave_sync();
+  __syncthreads();
   // (3) x-pencils (y, z): S_x^T, scale by (l_x + l_y + l_z)^{-1}, S_x
-#pragma unroll
-  for (int ro = 0; ro < ROUNDS; ++ro) {
-    const int l = lane + 64 * ro;
+  {
+    const int l = lane;
     if (l < M2) {
       const int y = l % M, z = l / M;
       T v[M], w[M];
@@ -230,11 +224,10 @@ __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r,
       for (int a = 0; a < M; ++a) t[z * M2 + y * M + a] = v[a];
     }
   }
-  wave_sync();
+  __syncthreads();
   // (4) y-pencils: S_y
-#pragma unroll
-  for (int ro = 0; ro < ROUNDS; ++ro) {
-    const int l = lane + 64 * ro;
+  {
+    const int l = lane;
     if (l < M2) {
       const int x = l % M, z = l / M;
       T v[M], w[M];
@@ -245,13 +238,12 @@ __global__ void __launch_bounds__(64) k_fdm_patch3_wave(const T* __restrict__ r,
       for (int a = 0; a < M; ++a) t[z * M2 + a * M + x] = w[a];
     }
   }
-  wave_sync();
+  __syncthreads();
   // (5) z-pencils: S_z, then the patch solution, patch-major (m^3 values, x
   // fastest): consecutive lanes store consecutive values
   T* wp = W + pid * M3;
-#pragma unroll
-  for (int ro = 0; ro < ROUNDS; ++ro) {
-    const int l = lane + 64 * ro;
+  {
+    const int l = lane;
     if (l < M2) {
       T v[M], w[M];
 #pragma unroll
@@ -274,11 +266,11 @@ static fe_status patch_wave_typed(const Level& L, const T* r, T* W, const T* eig
   if (np == 0) return FE_OK;
   ProfScope ps("fdm_patch", s);
   if (per_patch)
-    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, true>), dim3((unsigned)np), dim3(64), 0, s, r, W, eig, il, scale,
-                       L.n);
+    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, true>), dim3((unsigned)np), dim3(WavePatch<K>::THREADS), 0, s, r, W,
+                       eig, il, scale, L.n);
   else
-    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, false>), dim3((unsigned)np), dim3(64), 0, s, r, W, eig, il, scale,
-                       L.n);
+    hipLaunchKernelGGL((k_fdm_patch3_wave<T, K, false>), dim3((unsigned)np), dim3(WavePatch<K>::THREADS), 0, s, r, W,
+                       eig, il, scale, L.n);
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
 }
