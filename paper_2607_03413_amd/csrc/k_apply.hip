@@ -36,12 +36,7 @@ __global__ void __launch_bounds__(256) k_apply_cart3(const T* __restrict__ x, T*
   const int64_t cell = (int64_t)blockIdx.x * CPB + c;
   const bool active = cell < n_cells;
   int cx = 0, cy = 0, cz = 0;
-  if (active) {
-    cx = (int)(cell % n);
-    const int64_t t = cell / n;
-    cy = (int)(t % n);
-    cz = (int)(t / n);
-  }
+  if (active) cell_coords3<TPC % 64 == 0>(cell, n, cx, cy, cz);   // K = 8: one cell per wavefront
   T* la = sa + c * CS;
   T* lb = sb + c * CS;
 

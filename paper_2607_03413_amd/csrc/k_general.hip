@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
   const int64_t cell = (int64_t)blockIdx.x * CPB + c;
   const bool active = cell < n_cells;
   int cx = 0, cy = 0, cz = 0;
-  if (active) { cx = (int)(cell % n); const int64_t t = cell / n; cy = (int)(t % n); cz = (int)(t / n); }
+  if (active) cell_coords3<TPC % 64 == 0>(cell, n, cx, cy, cz);
   T* l0 = s0 + c * CS;
   T* l1 = s1 + c * CS;
   T* l2 = s2 + c * CS;

@@ -7,12 +7,26 @@
 
 namespace fe {
 
+// A K x K matrix of T that does not fit in the scalar registers next to
+// everything else (more than 24 of them): its rows are fetched where they are
+// used.  Without this the compiler loads the whole matrix up front and parks
+// the entries in vector-register lanes (one readlane per use).
+template <typename T, int K>
+struct RowFetch {
+  static constexpr bool value = K * K * (int)sizeof(T) > 4 * 24;
+};
+template <typename T, int K>
+__device__ __forceinline__ void row_fence() {
+  if (RowFetch<T, K>::value) asm volatile("" ::: "memory");
+}
+
 // Pencil matrix-vector product out = M in, M row-major K x K at a uniform
 // (wave-invariant) address, so the entries are fetched with scalar loads.
 template <typename T, int K>
 __device__ __forceinline__ void pencil_mv(const T* __restrict__ M, const T (&in)[K], T (&out)[K]) {
 #pragma unroll
   for (int i = 0; i < K; ++i) {
+    row_fence<T, K>();
     T s = M[i * K] * in[0];
 #pragma unroll
     for (int j = 1; j < K; ++j) s = fma(M[i * K + j], in[j], s);
@@ -25,6 +39,7 @@ template <typename T, int K>
 __device__ __forceinline__ void pencil_mtv(const T* __restrict__ M, const T (&in)[K], T (&out)[K]) {
 #pragma unroll
   for (int i = 0; i < K; ++i) {
+    row_fence<T, K>();
     T s = M[i] * in[0];
 #pragma unroll
     for (int j = 1; j < K; ++j) s = fma(M[j * K + i], in[j], s);
@@ -38,6 +53,7 @@ __device__ __forceinline__ void pencil_mv2(const T* __restrict__ A, const T (&ia
                                            const T* __restrict__ B, const T (&ib)[K], T (&out)[K]) {
 #pragma unroll
   for (int i = 0; i < K; ++i) {
+    row_fence<T, K>();
     T s = A[i * K] * ia[0];
 #pragma unroll
     for (int j = 1; j < K; ++j) s = fma(A[i * K + j], ia[j], s);
@@ -70,6 +86,20 @@ __device__ __forceinline__ AxisCopies axis_copies(int g, int n) {
     if (a.cnt == 1) { a.c[1] = a.c[0]; a.i[1] = a.i[0]; }
   }
   return a;
+}
+
+// Coordinates of cell `cell` of an n^3 mesh.  Cell indices fit in 32 bits
+// (problem creation bounds the cell-wise length by 2^33 values, so n^3 <=
+// 2^30); with a wavefront-uniform cell (UNIFORM) the divisions run on the
+// scalar unit.
+template <bool UNIFORM>
+__device__ __forceinline__ void cell_coords3(int64_t cell, int n, int& cx, int& cy, int& cz) {
+  int c = (int)cell;
+  if (UNIFORM) c = __builtin_amdgcn_readfirstlane(c);
+  const int t = c / n;
+  cx = c - t * n;
+  cy = t % n;
+  cz = t / n;
 }
 
 __device__ __forceinline__ bool on_boundary(int c, int i, int n, int k) {
