@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 # (dim, k, n): C1 is 2D Q2 16^2; the 3D cases span several blocks with ragged tails
 CASES = [(2, 2, 16), (2, 1, 5), (2, 5, 3), (3, 1, 5), (3, 2, 3), (3, 3, 4), (3, 3, 5), (3, 4, 3), (3, 7, 2),
-         (3, 8, 2)]
+         (3, 8, 2), (2, 3, 1), (3, 3, 1), (3, 7, 1)]   # n = 1: a single cell, every node on the boundary
 
 
 def dev(a, dtype=torch.float64):
