@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-deformed", action="store_true")
     ap.add_argument("--only-step", action="store_true", help="time the headline step only (for profilers)")
     ap.add_argument("--with-copy", action="store_true", help="with --only-step: add a plain copy kernel of known size")
+    ap.add_argument("--only-pcg", action="store_true", help="run the Q7 32^3 MG-PCG solves only (for profilers)")
     ap.add_argument("--step-config", default="q3", choices=["q3", "q7", "q7f32", "q3f32"],
                     help="with --only-step: which step to run (Q3 64^3 or Q7 32^3, FP64 or FP32)")
     return ap.parse_args()
@@ -302,6 +303,9 @@ def main():
         sys.exit(1)
     from paper_2607_03413_amd import fe
 
+    if args.only_pcg:
+        print(json.dumps(bench_pcg(fe)))
+        return
     if args.only_step and args.step_config != "q3":
         deg, n = (7, 32) if args.step_config.startswith("q7") else (3, 64)
         dtype = torch.float32 if args.step_config.endswith("f32") else torch.float64
