@@ -516,9 +516,10 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
 // (x across lanes, y through LDS, z through partial sums in the output).
 //
 // A row of 32 patches touches 33 cells; the upper boundary cell of the mesh
-// (x = n-1) has no patch of its own and is written by the lane of patch n-1.
-// Blocks are 8 rows (one wavefront each) of which the first recomputes the
-// last row of the tile below.
+// (x = n-1) has no patch of its own and is assembled by the lane of patch
+// n-1, then stored with the row's other cells.  Blocks are 8 rows (one
+// wavefront each) of which the first recomputes the last row of the tile
+// below.
 template <typename T, int K, int WY_ = 8, int NBUF_ = 3>
 struct SplitPatch {
   using value_type = T;
@@ -710,8 +711,10 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
   const bool pxy = vx <= n - 1 && vy <= n - 1;
   const int cx = vx - 1, cy = vy - 1;
   const bool own_y = cy <= n - 1 && (wy >= 1 || ty == 0);
-  const bool own_xy = own_y && vx <= n - 1 && cx >= own_lo && cx <= own_hi;
-  const bool ext_xy = own_y && vx == n - 1;   // also writes the boundary cell x = n-1
+  // The boundary cell x = n-1 is the cell of the lane on vertex n (no patch,
+  // completed by the x merge) when the tile reaches that far; otherwise
+  // (X0 + 32 = n) the lane of patch n-1 assembles it as an extra cell.
+  const bool ext = last_tx && vx == n - 1 && X0 + SP::NPX == n;
   const int C0 = tz * zlen, C1 = min(n, C0 + zlen);
   const int lane_off = split_offset<T, NXC, NCH>(wy, pi, 0);
 
@@ -720,6 +723,25 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
   const T cm = pxy && !half ? T(1) : T(0), cn = pxy ? (half ? T(-1) : T(1)) : T(0);
   const T sg = half ? T(-1) : T(1);
   const T xm = pi == 0 ? T(0) : T(1);   // lane 32 must not take the shifted value of lane 31
+
+  // merge stores: lane (tq, tc) writes chunk tc of the plane of cell X0-1+q,
+  // q = t*PPI + tq, t < NST; step t = NST, lanes tq = 0, writes the extra
+  // boundary cell X0+31 = n-1.  Bit t of ownm: this block owns it.
+  constexpr int VPC = SP::VPC, PPI = 64 / NCH, NST = SP::NPX / PPI, TSTR = K2 + VPC;
+  static_assert(SP::NPX % PPI == 0 && (SP::NPX + 1) * TSTR * WY <= SLICE, "store staging must fit one slice buffer");
+  typedef T vec_t __attribute__((ext_vector_type(VPC)));
+  typedef __attribute__((address_space(3))) vec_t lds_vec_t;
+  const int tq = lane / NCH, tc = lane - tq * NCH;
+  int ownm = 0;
+#pragma unroll
+  for (int t = 0; t < NST; ++t) {
+    const int q = t * PPI + tq, cq = X0 - 1 + q;
+    if (own_y && X0 + q <= n && cq >= own_lo && cq <= own_hi) ownm |= 1 << t;
+  }
+  if (own_y && last_tx && tq == 0 && X0 + SP::NPX == n) ownm |= 1 << NST;
+  // wavefront-private staging area (padded rows: conflict-free deposits)
+  __attribute__((address_space(3))) T* const stg =
+      (__attribute__((address_space(3))) T*)buf(NBUF - 1) + wy * ((SP::NPX + 1) * TSTR);
 
   for (int e = tid; e < SP::ILS; e += 64 * WY) {
     const int h = e / (NE * M * M), rest = e - h * (NE * M * M), j = rest / (M * M), yx = rest - j * (M * M);
@@ -753,11 +775,12 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
           stage_slice_split<SP>(buf(sl % NBUF), r, sl + NBUF, vz, X0, Y0, n, tid);
         }
       }
-      // every buffer has been read: fetch the next level's first slices
+      // every buffer has been read: fetch the next level's first slices (the
+      // last buffer is the merge's store staging area and is filled after it)
       lds_barrier();
       if (next_ok) {
 #pragma unroll
-        for (int s = 0; s < NBUF; ++s) stage_slice_split<SP>(buf(s), r, s, vz + 1, X0, Y0, n, tid);
+        for (int s = 0; s < NBUF - 1; ++s) stage_slice_split<SP>(buf(s), r, s, vz + 1, X0, Y0, n, tid);
       }
       {
         const T* __restrict__ SE = Seo;
@@ -820,7 +843,7 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
       if (next_ok) {
         lds_barrier();
 #pragma unroll
-        for (int s = 0; s < NBUF; ++s) stage_slice_split<SP>(buf(s), r, s, vz + 1, X0, Y0, n, tid);
+        for (int s = 0; s < NBUF - 1; ++s) stage_slice_split<SP>(buf(s), r, s, vz + 1, X0, Y0, n, tid);
       }
     }
 
@@ -829,15 +852,13 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
     // Plane az holds nodes of cell layer vz-1 (iz = az + 1) for az <= k-1 and
     // of layer vz (iz = az - k + 1) for az >= k-1.
     const int64_t cell_xy = (int64_t)cx + (int64_t)n * cy;
-    T* out_lo = z + (cell_xy + (int64_t)n * n * (vz - 1)) * K3;
-    T* out_hi = z + (cell_xy + (int64_t)n * n * vz) * K3;
     const bool lo_ok = vz - 1 >= C0, hi_ok = vz < C1;
-    const bool has_ext = last_tx;   // block-uniform: the tile holds patch n-1
+    // store orientation: chunk tc of the plane of cell X0-1+q, q = t*PPI + tq,
+    // at st_lo + t*PPI*K3 (layer vz-1) and st_hi + t*PPI*K3 (layer vz)
+    T* const st_lo = z + (cell_xy - pi + tq + (int64_t)n * n * (vz - 1)) * K3 + tc * VPC;
+    T* const st_hi = st_lo + (int64_t)n * n * K3;
 #pragma unroll
     for (int a = 0; a <= C; ++a) {
-      const bool low = half == 0;
-      const bool rmw = low && a < C && own_xy && lo_ok;   // add to the partial sums of the level below
-      const bool ermw = low && a < C && ext_xy && lo_ok;
       if (a > 0) lds_barrier();   // the row above has read the previous plane
       // x merge row by row; rows k-1.. go to the row above, rows ..k-1 stay
       T Xk[k][K];
@@ -862,18 +883,18 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
 #pragma unroll
           for (int i = 0; i < K; ++i) xch[((b - k + 1) * K + i) * (64 * (WY - 1)) + tid] = X[i];
         }
-        if (has_ext && vx == n - 1) {
+        if (last_tx && ext) {
           // boundary cell x = n-1: only patch n-1 covers it along x
 #pragma unroll
           for (int i = 0; i < k; ++i) xeb[((b * k + i) * WY + wy) * 2 + half] = v[k - 1 + i];
         }
       }
-      T old[K][K] = {};   // defined on every path: no value is carried across levels
-      if (rmw) {
+      // partial sums of the level below, read in the store orientation
+      vec_t old[NST];
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-#pragma unroll
-          for (int i = 0; i < K; ++i) old[j][i] = out_lo[(a + 1) * K2 + j * K + i];
+      for (int t = 0; t < NST; ++t) {
+        old[t] = vec_t{};   // defined on every path: no value is carried across levels
+        if (a < C && lo_ok && ((ownm >> t) & 1)) old[t] = *reinterpret_cast<const vec_t*>(st_lo + t * PPI * K3 + (a + 1) * K2);
       }
       lds_barrier();
       T Y[K][K];
@@ -890,80 +911,72 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
       // lower half: planes 0..k-2 complete layer vz-1, the middle plane is the
       // vertex plane of both layers; upper half: the planes above the middle
       // start layer vz as partial sums
-      if (low) {
-        if (a < C) {
-          if (rmw) {
+      // Stores: a half-wavefront deposits its 32 cell planes in the staging
+      // area and the whole wavefront writes them out as 16-byte chunks, NCH
+      // consecutive lanes per contiguous plane.
+      auto deposit = [&](int h) {
+        if (half == h) {
 #pragma unroll
-            for (int j = 0; j < K; ++j)
+          for (int c = 0; c < NCH; ++c) {
+            vec_t v;
 #pragma unroll
-              for (int i = 0; i < K; ++i) out_lo[(a + 1) * K2 + j * K + i] = old[j][i] + Y[j][i];
-          }
-        } else {
-          if (own_xy && lo_ok) {
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-#pragma unroll
-              for (int i = 0; i < K; ++i) out_lo[k * K2 + j * K + i] = Y[j][i];
-          }
-          if (own_xy && hi_ok) {
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-#pragma unroll
-              for (int i = 0; i < K; ++i) out_hi[j * K + i] = Y[j][i];
+            for (int e = 0; e < VPC; ++e) v[e] = Y[(c * VPC + e) / K][(c * VPC + e) % K];
+            *reinterpret_cast<lds_vec_t*>(stg + pi * TSTR + c * VPC) = v;
           }
         }
-      } else if (a < C && own_xy && hi_ok) {
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-#pragma unroll
-          for (int i = 0; i < K; ++i) out_hi[(k - 1 - a) * K2 + j * K + i] = Y[j][i];
-      }
-      if (has_ext && ext_xy && (low || a < C)) {
-        T YE[K][K];
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-#pragma unroll
-          for (int i = 0; i < K; ++i) {
-            if (i == k) { YE[j][i] = T(0); continue; }
-            T lo = T(0);
-            if (j < k && wy >= 1) lo = xeb[(((k - 1 + j) * k + i) * WY + wy - 1) * 2 + half];
-            if (j == 0) YE[j][i] = lo;
-            else if (j < k) YE[j][i] = lo + xeb[(((j - 1) * k + i) * WY + wy) * 2 + half];
-            else YE[j][i] = xeb[(((k - 1) * k + i) * WY + wy) * 2 + half];
+        if (last_tx && X0 + SP::NPX == n && half == h && pi < K2) {
+          // the extra boundary cell, one value per lane: rows of patch n-1
+          // from this wavefront and the one below, x node k on the boundary
+          const int j = pi / K, i = pi - j * K;
+          T y = T(0);
+          if (i < k) {
+            const T lo = (j < k && wy >= 1) ? xeb[(((k - 1 + j) * k + i) * WY + wy - 1) * 2 + half] : T(0);
+            if (j == 0) y = lo;
+            else if (j < k) y = lo + xeb[(((j - 1) * k + i) * WY + wy) * 2 + half];
+            else y = xeb[(((k - 1) * k + i) * WY + wy) * 2 + half];
           }
-        T* elo = out_lo + K3;
-        T* ehi = out_hi + K3;
-        if (low) {
-          if (a < C) {
-            if (ermw) {
+          stg[SP::NPX * TSTR + pi] = y;
+        }
+        __builtin_amdgcn_wave_barrier();
+      };
+      auto fetch = [&](int t) -> vec_t {
+        return *reinterpret_cast<const lds_vec_t*>(stg + (t * PPI + tq) * TSTR + tc * VPC);
+      };
+      if (a < C) {
+        // lower half: planes a+1 of layer vz-1 complete the partial sums
+        deposit(0);
 #pragma unroll
-              for (int j = 0; j < K; ++j)
+        for (int t = 0; t < NST; ++t)
+          if (lo_ok && ((ownm >> t) & 1)) *reinterpret_cast<vec_t*>(st_lo + t * PPI * K3 + (a + 1) * K2) = fetch(t) + old[t];
+        if (lo_ok && ((ownm >> NST) & 1)) {
+          // boundary cell: added in memory (no load, so no wait behind the stores above)
+          const vec_t v = fetch(NST);
+          T* const e = st_lo + NST * PPI * K3 + (a + 1) * K2;
 #pragma unroll
-                for (int i = 0; i < K; ++i) elo[(a + 1) * K2 + j * K + i] += YE[j][i];
-            }
-          } else {
-            if (lo_ok) {
+          for (int i = 0; i < VPC; ++i) unsafeAtomicAdd(e + i, v[i]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // upper half: planes k-1-a of layer vz start as partial sums
+        deposit(1);
 #pragma unroll
-              for (int j = 0; j < K; ++j)
+        for (int t = 0; t <= NST; ++t)
+          if (hi_ok && ((ownm >> t) & 1)) *reinterpret_cast<vec_t*>(st_hi + t * PPI * K3 + (k - 1 - a) * K2) = fetch(t);
+      } else {
+        // the middle plane: the vertex plane of both layers
+        deposit(0);
 #pragma unroll
-                for (int i = 0; i < K; ++i) elo[k * K2 + j * K + i] = YE[j][i];
-            }
-            if (hi_ok) {
-#pragma unroll
-              for (int j = 0; j < K; ++j)
-#pragma unroll
-                for (int i = 0; i < K; ++i) ehi[j * K + i] = YE[j][i];
-            }
-          }
-        } else if (hi_ok) {
-#pragma unroll
-          for (int j = 0; j < K; ++j)
-#pragma unroll
-            for (int i = 0; i < K; ++i) ehi[(k - 1 - a) * K2 + j * K + i] = YE[j][i];
+        for (int t = 0; t <= NST; ++t) {
+          if (!((ownm >> t) & 1)) continue;
+          const vec_t v = fetch(t);
+          if (lo_ok) *reinterpret_cast<vec_t*>(st_lo + t * PPI * K3 + k * K2) = v;
+          if (hi_ok) *reinterpret_cast<vec_t*>(st_hi + t * PPI * K3) = v;
         }
       }
+      __builtin_amdgcn_wave_barrier();
     }
-    lds_barrier();   // the exchange area is rewritten by the next level
+    // the exchange area and the store staging area are rewritten by the next level
+    lds_barrier();
+    if (next_ok) stage_slice_split<SP>(buf(NBUF - 1), r, NBUF - 1, vz + 1, X0, Y0, n, tid);
   }
   __builtin_amdgcn_s_waitcnt(0);
 }
