@@ -897,6 +897,19 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
         if (a < C && lo_ok && ((ownm >> t) & 1)) old[t] = *reinterpret_cast<const vec_t*>(st_lo + t * PPI * K3 + (a + 1) * K2);
       }
       lds_barrier();
+      // the extra boundary cell, one value per lane (pi < K2, both halves):
+      // rows of patch n-1 from this wavefront and the one below, x node k on
+      // the boundary; read here so that the latency overlaps the merge below
+      T ye = T(0);
+      if (last_tx && X0 + SP::NPX == n && pi < K2) {
+        const int j = pi / K, i = pi - j * K;
+        if (i < k) {
+          const T lo = (j < k && wy >= 1) ? xeb[(((k - 1 + j) * k + i) * WY + wy - 1) * 2 + half] : T(0);
+          if (j == 0) ye = lo;
+          else if (j < k) ye = lo + xeb[(((j - 1) * k + i) * WY + wy) * 2 + half];
+          else ye = xeb[(((k - 1) * k + i) * WY + wy) * 2 + half];
+        }
+      }
       T Y[K][K];
 #pragma unroll
       for (int j = 0; j < K; ++j)
@@ -924,19 +937,7 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
             *reinterpret_cast<lds_vec_t*>(stg + pi * TSTR + c * VPC) = v;
           }
         }
-        if (last_tx && X0 + SP::NPX == n && half == h && pi < K2) {
-          // the extra boundary cell, one value per lane: rows of patch n-1
-          // from this wavefront and the one below, x node k on the boundary
-          const int j = pi / K, i = pi - j * K;
-          T y = T(0);
-          if (i < k) {
-            const T lo = (j < k && wy >= 1) ? xeb[(((k - 1 + j) * k + i) * WY + wy - 1) * 2 + half] : T(0);
-            if (j == 0) y = lo;
-            else if (j < k) y = lo + xeb[(((j - 1) * k + i) * WY + wy) * 2 + half];
-            else y = xeb[(((k - 1) * k + i) * WY + wy) * 2 + half];
-          }
-          stg[SP::NPX * TSTR + pi] = y;
-        }
+        if (last_tx && X0 + SP::NPX == n && half == h && pi < K2) stg[SP::NPX * TSTR + pi] = ye;
         __builtin_amdgcn_wave_barrier();
       };
       auto fetch = [&](int t) -> vec_t {
