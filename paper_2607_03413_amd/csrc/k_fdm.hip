@@ -248,42 +248,54 @@ __global__ void __launch_bounds__(256) k_fdm_patch3(const T* __restrict__ r, T* 
 // patches at the cell's (up to 8) corners from the slot-split buffer, in the
 // order bz, by, bx ascending (= patch vertices ascending, the same for every
 // copy of a node, so copies come out bit-identical), and writes its own entry:
-// consecutive threads write consecutive addresses, whole cache lines.
+// consecutive threads write consecutive addresses, whole cache lines.  A block
+// holds SumSlots<K>::CPB consecutive cells of an x-row (grid: x-groups, n, n),
+// so no thread divides by n.  No load is branched around (a branch per load
+// made each one wait for its data before the next was issued): an absent
+// patch is read at W[0] and added times 0, an exact 0.
+template <int K>
+struct SumSlots {
+  static constexpr int K3 = K * K * K;
+  static constexpr int CPB = K3 >= 64 ? 1 : 64 / K3;   // cells per block
+  static constexpr int THREADS = CPB * K3;
+};
+
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_fdm_sum_slots3(const T* __restrict__ W, T* __restrict__ z, int n,
-                                                        int64_t len) {
+__global__ void __launch_bounds__(SumSlots<K>::THREADS) k_fdm_sum_slots3(const T* __restrict__ W, T* __restrict__ z, int n) {
   constexpr int k = K - 1;
   constexpr int k3 = k * k * k;
   constexpr int K3 = K * K * K;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= len) return;
-  const int64_t cell = e / K3;
-  const int loc = (int)(e - cell * K3);
+  const int cl = threadIdx.x / K3, loc = threadIdx.x - cl * K3;
+  const int cx = blockIdx.x * SumSlots<K>::CPB + cl, cy = blockIdx.y, cz = blockIdx.z;
+  if (cx >= n) return;
   const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
-  const int cx = (int)(cell % n);
-  const int64_t t = cell / n;
-  const int cy = (int)(t % n), cz = (int)(t / n);
   const int nv = n - 1;
+  T* const out = z + ((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc;
+  if (nv < 1) {   // no patch at all (and possibly no scratch)
+    *out = T(0);
+    return;
+  }
   T s = T(0);
 #pragma unroll
   for (int bz = 0; bz < 2; ++bz) {
     const int vz = cz + bz, jz = iz - bz;
-    if (vz < 1 || vz > nv || jz < 0 || jz >= k) continue;
+    const bool okz = vz >= 1 && vz <= nv && jz >= 0 && jz < k;
 #pragma unroll
     for (int by = 0; by < 2; ++by) {
       const int vy = cy + by, jy = iy - by;
-      if (vy < 1 || vy > nv || jy < 0 || jy >= k) continue;
+      const bool oky = vy >= 1 && vy <= nv && jy >= 0 && jy < k;
 #pragma unroll
       for (int bx = 0; bx < 2; ++bx) {
         const int vx = cx + bx, jx = ix - bx;
-        if (vx < 1 || vx > nv || jx < 0 || jx >= k) continue;
+        const bool use = okz && oky && vx >= 1 && vx <= nv && jx >= 0 && jx < k;
         const int64_t pid = (vx - 1) + (int64_t)nv * ((vy - 1) + (int64_t)nv * (vz - 1));
         const int slot = (1 - bx) + 2 * (1 - by) + 4 * (1 - bz);
-        s += W[pid * (8 * k3) + slot * k3 + jx + k * (jy + k * jz)];
+        const int64_t idx = (pid * (8 * k3) + slot * k3 + jx + k * (jy + k * jz)) & -(int64_t)use;
+        s = fma(W[idx], use ? T(1) : T(0), s);
       }
     }
   }
-  z[e] = s;
+  *out = s;
 }
 
 template <typename T, int K, bool PER_PATCH>
@@ -408,42 +420,75 @@ __global__ void __launch_bounds__(256) k_fdm_sum2(const T* __restrict__ W, T* __
 // The sum runs over (z, y, x) patch candidates in ascending vertex order,
 // which depends only on the node: all copies receive identical values.
 template <typename T, int K>
-__global__ void __launch_bounds__(K * K * K) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n) {
+__global__ void __launch_bounds__((K * K + 63) / 64 * 64) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n) {
   constexpr int k = K - 1;
   constexpr int M = 2 * k - 1;
   constexpr int MP = M * M * M;
   constexpr int NL = K * K * K;
-  // one block per cell: the cell and its candidate patches are block-uniform
-  // (scalar arithmetic); each thread owns one node of the cell
-  const int cell = blockIdx.x;
-  const int cx = cell % n, cy = (cell / n) % n, cz = cell / (n * n);
+  // one block per cell, grid (n, n, n); a lane owns the z-line (ix, iy) of
+  // the cell.  The cell and its candidate patches are block-uniform, and so
+  // is, per z node, which of the two patch layers along z covers it.
+  const int cx = blockIdx.x, cy = blockIdx.y, cz = blockIdx.z;
   const int loc = threadIdx.x;
-  const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+  const bool act = loc < K * K;
+  const int ix = loc % K, iy = loc / K;
   const int nv = n - 1;
   // candidate c = 0: vertex = cell (offset k-1+i), c = 1: vertex = cell+1 (offset i-1)
-  const int c3[3] = {cx, cy, cz}, i3[3] = {ix, iy, iz};
-  int off[3][2];
-  bool ok[3][2];
+  const int c2[2] = {cx, cy}, i2[2] = {ix, iy};
+  int off[2][2];
+  bool ok[2][2];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    off[a][0] = k - 1 + i3[a];
-    ok[a][0] = i3[a] < k && c3[a] >= 1;
-    off[a][1] = i3[a] - 1;
-    ok[a][1] = i3[a] > 0 && c3[a] + 1 <= nv;
+  for (int a = 0; a < 2; ++a) {
+    off[a][0] = k - 1 + i2[a];
+    ok[a][0] = act && i2[a] < k && c2[a] >= 1;
+    off[a][1] = i2[a] - 1;
+    ok[a][1] = act && i2[a] > 0 && c2[a] + 1 <= nv;
   }
-  T s = T(0);
+  // patch (cx-1, cy-1, cz-1) and the strides to its neighbours along y and z
+  const int64_t p000 = (int64_t)(cx - 1) + (int64_t)nv * ((cy - 1) + (int64_t)nv * (cz - 1));
+  const int64_t sy = nv, sz = (int64_t)nv * nv;
+  T* const zc = z + ((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * NL;
+  if (nv < 1) {   // no patch at all (and possibly no scratch)
 #pragma unroll
-  for (int bz = 0; bz < 2; ++bz)
+    for (int iz = 0; iz < K; ++iz)
+      if (act) zc[iz * K * K + loc] = T(0);
+    return;
+  }
+  // Patches in ascending vertex order (z, then y, then x), as every copy of a
+  // node sums them.  No load is branched around (a branch per load made each
+  // one wait for its data before the next was issued): a lane without that
+  // patch reads W[0] and adds it times 0, an exact 0 that leaves the sum
+  // unchanged, and the stores come after all loads, so that all of them can
+  // be in flight.
+  // (the z-layer tests are uniform; computed from a vector copy of cz they
+  // become selects rather than branches that would split the loads into groups)
+  int czv = cz;
+  asm volatile("" : "+v"(czv));
+  const bool zlo = czv >= 1, zhi = czv + 1 <= nv;
+  T acc[K];
 #pragma unroll
-    for (int by = 0; by < 2; ++by)
+  for (int iz = 0; iz < K; ++iz) {
+    T s = T(0);
 #pragma unroll
-      for (int bx = 0; bx < 2; ++bx) {
-        const bool use = ok[2][bz] && ok[1][by] && ok[0][bx];
-        const int64_t pid = (cx + bx - 1) + (int64_t)nv * ((cy + by - 1) + (int64_t)nv * (cz + bz - 1));
-        const int o = off[0][bx] + M * (off[1][by] + M * off[2][bz]);
-        if (use) s += W[pid * MP + o];   // masked load: no access for absent patches
-      }
-  z[(int64_t)cell * NL + loc] = s;
+    for (int bz = 0; bz < 2; ++bz) {
+      const bool okz = bz == 0 ? (iz < k && zlo) : (iz > 0 && zhi);
+      const int oz = bz == 0 ? k - 1 + iz : iz - 1;
+#pragma unroll
+      for (int by = 0; by < 2; ++by)
+#pragma unroll
+        for (int bx = 0; bx < 2; ++bx) {
+          const bool use = okz && ok[1][by] && ok[0][bx];
+          const int o = off[0][bx] + M * (off[1][by] + M * oz);
+          const int64_t idx = ((p000 + bx + by * sy + bz * sz) * MP + o) & -(int64_t)use;
+          s = fma(W[idx], use ? T(1) : T(0), s);
+        }
+    }
+    acc[iz] = s;
+  }
+  if (act) {
+#pragma unroll
+    for (int iz = 0; iz < K; ++iz) zc[iz * K * K + loc] = acc[iz];
+  }
 }
 
 bool fused_patch_supported(const fe_problem* p, bool per_patch);
@@ -486,10 +531,11 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
     }
     ProfScope ps2("fdm_sum", s);
     if (patch_wave_supported(p, per_patch))   // patch-major solutions
-      hipLaunchKernelGGL((k_fdm_sum_pm3<T, K>), dim3((unsigned)L.n_cells), dim3(K * K * K), 0, s, W, z, L.n);
+      hipLaunchKernelGGL((k_fdm_sum_pm3<T, K>), dim3((unsigned)L.n, (unsigned)L.n, (unsigned)L.n), dim3((K * K + 63) / 64 * 64), 0, s, W, z, L.n);
     else                                      // slot-split solutions
-      hipLaunchKernelGGL((k_fdm_sum_slots3<T, K>), dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, s, W, z,
-                         L.n, L.len);
+      hipLaunchKernelGGL((k_fdm_sum_slots3<T, K>),
+                         dim3((unsigned)((L.n + SumSlots<K>::CPB - 1) / SumSlots<K>::CPB), (unsigned)L.n, (unsigned)L.n),
+                         dim3(SumSlots<K>::THREADS), 0, s, W, z, L.n);
   } else {
     const int64_t np = nv * nv;
     if (np > 0) {
