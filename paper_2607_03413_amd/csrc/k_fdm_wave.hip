@@ -162,9 +162,14 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const
       const int x = l % M, y = l / M;
       const AxisCopies cx = wave_axis_copies<K>(x), cy = wave_axis_copies<K>(y);
       T v[M], w[M];
+      // Both copies along x and y are loaded in every lane (a node with one
+      // copy reads it twice and weights the second by 0): a load behind a
+      // lane-dependent branch waits for its data before the next is issued.
+      // fma(b, 1, a) rounds as a + b, so the sums are those of the copies.
+      const T wx = cx.cnt == 2 ? T(1) : T(0), wy = cy.cnt == 2 ? T(1) : T(0);
 #pragma unroll
       for (int z = 0; z < M; ++z) {
-        const AxisCopies cz = wave_axis_copies<K>(z);
+        const AxisCopies cz = wave_axis_copies<K>(z);   // compile-time after unrolling
         T zs = T(0);
 #pragma unroll
         for (int sz = 0; sz < 2; ++sz) {
@@ -172,11 +177,9 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const
           T ys = T(0);
 #pragma unroll
           for (int sy = 0; sy < 2; ++sy) {
-            if (sy >= cy.cnt) break;
             const T* cb = rc + cz.c[sz] * sz_cells + cy.c[sy] * sy_cells + K * (cy.i[sy] + K * cz.i[sz]);
-            T xs = cb[cx.c[0] * K3 + cx.i[0]];
-            if (cx.cnt == 2) xs += cb[cx.c[1] * K3 + cx.i[1]];
-            ys = sy == 0 ? xs : ys + xs;
+            const T xs = fma(cb[cx.c[1] * K3 + cx.i[1]], wx, cb[cx.c[0] * K3 + cx.i[0]]);
+            ys = sy == 0 ? xs : fma(xs, wy, ys);
           }
           zs = sz == 0 ? ys : zs + ys;
         }
