@@ -5,8 +5,10 @@
 // z = G sum_p R_p^T (S_x x S_y x S_z) (L_x + L_y + L_z)^{-1} (S_x x S_y x S_z)^T R_p G^T r
 // (vertex-patch smoother admissible by eq. precond_consistency, Sec. 2.1;
 // fast diagonalization of the separable patch operator).  The 1D factors
-// are uniform over a wavefront, so S and the eigenvalues are read through
-// the scalar cache and every FMA takes one operand from a scalar register:
+// are uniform over a wavefront: the Cartesian S (even/odd halves) and the
+// eigenvalues are read through the scalar cache and every FMA takes one
+// operand from a scalar register; per-patch factors (three dense m x m
+// matrices) are staged in LDS and read as broadcasts, a row at a time:
 //   * lane l owns pencil l (a line of m values) of every pass, so a patch is
 //     spread over several wavefronts and each pass is one round; the LDS
 //     array of a patch limits how many patches a CU holds, not the lanes;
@@ -35,6 +37,12 @@ struct WavePatch {
   static constexpr int THREADS = (M2 + 63) / 64 * 64;   // one lane per pencil, whole wavefronts
   static constexpr int C = k - 1;         // middle node
   static constexpr int NE = C + 1, NO = C;
+};
+// LDS row stride of a per-patch factor matrix: M rounded up to 16 bytes
+template <typename T, int M>
+struct FactorRows {
+  static constexpr int VPC = 16 / (int)sizeof(T);
+  static constexpr int MS = (M + VPC - 1) / VPC * VPC;
 };
 
 // 1 / x: hardware reciprocal refined by Newton steps r <- r (2 - x r).
@@ -107,6 +115,37 @@ __device__ __forceinline__ void line_apply(const T* __restrict__ S, const T (&x)
   }
 }
 
+// The same for per-patch factors staged in LDS (rows of MS >= M values, a
+// multiple of 16 bytes, so that a row is read 16 bytes at a time; every lane
+// reads the same address, a broadcast).  The products are accumulated in the
+// order of line_apply (a ascending), so the results are the same.
+template <typename T>
+using lds_cptr = const __attribute__((address_space(3))) T*;
+template <typename T, int M, int MS, bool FWD>
+__device__ __forceinline__ void line_apply_lds(lds_cptr<T> S, const T (&x)[M], T (&y)[M]) {
+  // one row of S in flight at a time (otherwise the whole matrix is loaded
+  // into vector registers up front)
+  if (FWD) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) y[i] = S[i] * x[0];
+#pragma unroll
+    for (int a = 1; a < M; ++a) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < M; ++i) y[i] = fma(S[a * MS + i], x[a], y[i]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      __builtin_amdgcn_sched_barrier(0);
+      T s = S[i * MS] * x[0];
+#pragma unroll
+      for (int a = 1; a < M; ++a) s = fma(S[i * MS + a], x[a], s);
+      y[i] = s;
+    }
+  }
+}
+
 // Copies of patch-local node a (0 <= a <= 2k-2) along one axis: cell slot
 // (0 = lower cell, 1 = upper cell) and local index, lower slot first.
 template <int K>
@@ -125,7 +164,10 @@ __device__ __forceinline__ AxisCopies wave_axis_copies(int a) {
 // otherwise (EO) the even/odd halves of the Cartesian S and the eigenvalues,
 // and il the level's table of scale / (l_x + l_y + l_z) in the same mode order.
 template <typename T, int K, bool PER_PATCH>
-__global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const T* __restrict__ r, T* __restrict__ W,
+// (per-patch FP32: at least 5 wavefronts per SIMD, measured faster than the
+// 128 VGPRs the compiler takes by itself for the residual loads)
+__global__ void __launch_bounds__(WavePatch<K>::THREADS)
+    __attribute__((amdgpu_waves_per_eu(PER_PATCH && sizeof(T) == 4 ? 5 : 1))) k_fdm_patch3_wave(const T* __restrict__ r, T* __restrict__ W,
                                                         const T* __restrict__ eig, const T* __restrict__ il,
                                                         T scale, int n) {
   using P = WavePatch<K>;
@@ -142,15 +184,25 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const
   const int64_t xcd = blockIdx.x & 7;
   const int64_t pid = xcd * q8 + (xcd < rem ? xcd : rem) + (blockIdx.x >> 3);
   const int vx = 1 + (int)(pid % nv), vy = 1 + (int)((pid / nv) % nv), vz = 1 + (int)(pid / ((int64_t)nv * nv));
-  const T *Sx, *Sy, *Sz, *lx, *ly, *lz;
+  const T* const Sx = eig;   // Cartesian: one even/odd S for all axes
+  const T* const Sy = eig;
+  const T* const Sz = eig;
+  // Per-patch factors: S_x, S_y, S_z and the eigenvalues of this patch go to
+  // LDS (scalar registers cannot hold three m x m matrices: they were spilled
+  // to vector lanes and read back one value at a time).
+  constexpr int MS = FactorRows<T, M>::MS;
+  __shared__ __attribute__((aligned(16))) T sF[PER_PATCH ? 3 * M * MS : 1];
+  __shared__ T sL[PER_PATCH ? 3 * M : 1];
   if (PER_PATCH) {
     const T* base = eig + pid * (3 * M2 + 3 * M);
-    Sx = base; Sy = base + M2; Sz = base + 2 * M2;
-    lx = base + 3 * M2; ly = lx + M; lz = ly + M;
-  } else {
-    Sx = Sy = Sz = eig;
-    lx = ly = lz = eig + P::NE * (P::C + 1) + P::NO * P::C;
+    for (int e = lane; e < 3 * M2; e += P::THREADS) {
+      const int q = e / M2, rr = e - q * M2, a = rr / M, i = rr - a * M;
+      sF[(q * M + a) * MS + i] = base[e];
+    }
+    for (int e = lane; e < 3 * M; e += P::THREADS) sL[e] = base[3 * M2 + e];
+    __syncthreads();
   }
+  const lds_cptr<T> fx = (lds_cptr<T>)sF, fy = fx + M * MS, fz = fy + M * MS;
   const int64_t c0 = (vx - 1) + (int64_t)n * ((vy - 1) + (int64_t)n * (vz - 1));
   const T* __restrict__ rc = r + c0 * K3;
   const int64_t sy_cells = (int64_t)n * K3, sz_cells = (int64_t)n * n * K3;
@@ -185,7 +237,8 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const
         }
         v[z] = zs;
       }
-      line_apply<T, M, EO, true>(Sz, v, w);
+      if (PER_PATCH) line_apply_lds<T, M, MS, true>(fz, v, w);
+      else line_apply<T, M, EO, true>(Sz, v, w);
 #pragma unroll
       for (int z = 0; z < M; ++z) t[z * M2 + y * M + x] = w[z];
     }
@@ -199,7 +252,8 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const
       T v[M], w[M];
 #pragma unroll
       for (int a = 0; a < M; ++a) v[a] = t[z * M2 + a * M + x];
-      line_apply<T, M, EO, true>(Sy, v, w);
+      if (PER_PATCH) line_apply_lds<T, M, MS, true>(fy, v, w);
+      else line_apply<T, M, EO, true>(Sy, v, w);
 #pragma unroll
       for (int a = 0; a < M; ++a) t[z * M2 + a * M + x] = w[a];
     }
@@ -213,16 +267,18 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const
       T v[M], w[M];
 #pragma unroll
       for (int a = 0; a < M; ++a) v[a] = t[z * M2 + y * M + a];
-      line_apply<T, M, EO, true>(Sx, v, w);
+      if (PER_PATCH) line_apply_lds<T, M, MS, true>(fx, v, w);
+      else line_apply<T, M, EO, true>(Sx, v, w);
       if (PER_PATCH) {
-        const T lyz = ly[y] + lz[z];
+        const T lyz = sL[M + y] + sL[2 * M + z];
 #pragma unroll
-        for (int a = 0; a < M; ++a) w[a] *= scale * recip(lx[a] + lyz);
+        for (int a = 0; a < M; ++a) w[a] *= scale * recip(sL[a] + lyz);
       } else {
 #pragma unroll
         for (int a = 0; a < M; ++a) w[a] *= il[l * M + a];
       }
-      line_apply<T, M, EO, false>(Sx, w, v);
+      if (PER_PATCH) line_apply_lds<T, M, MS, false>(fx, w, v);
+      else line_apply<T, M, EO, false>(Sx, w, v);
 #pragma unroll
       for (int a = 0; a < M; ++a) t[z * M2 + y * M + a] = v[a];
     }
@@ -236,7 +292,8 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const
       T v[M], w[M];
 #pragma unroll
       for (int a = 0; a < M; ++a) v[a] = t[z * M2 + a * M + x];
-      line_apply<T, M, EO, false>(Sy, v, w);
+      if (PER_PATCH) line_apply_lds<T, M, MS, false>(fy, v, w);
+      else line_apply<T, M, EO, false>(Sy, v, w);
 #pragma unroll
       for (int a = 0; a < M; ++a) t[z * M2 + a * M + x] = w[a];
     }
@@ -251,7 +308,8 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS) k_fdm_patch3_wave(const
       T v[M], w[M];
 #pragma unroll
       for (int z = 0; z < M; ++z) v[z] = t[z * M2 + l];
-      line_apply<T, M, EO, false>(Sz, v, w);
+      if (PER_PATCH) line_apply_lds<T, M, MS, false>(fz, v, w);
+      else line_apply<T, M, EO, false>(Sz, v, w);
 #pragma unroll
       for (int z = 0; z < M; ++z) wp[z * M2 + l] = w[z];
     }
