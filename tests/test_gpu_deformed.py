@@ -63,8 +63,10 @@ def test_general_load_vector(gpu_lib, k, n):
     assert relerr(host(b), g.load_vector().ravel()) < 1e-12
 
 
-@pytest.mark.parametrize("k,n", [(2, 3), (3, 4), (1, 4)])
+@pytest.mark.parametrize("k,n", [(2, 3), (3, 4), (1, 4), (7, 3)])
 def test_averaged_patch_inverse(gpu_lib, k, n):
+    """Per-patch separable factors (averaged geometry): k <= 3 on the slot-split
+    patch kernel, k = 7 on the one-lane-per-pencil kernel with its factors in LDS."""
     fe = gpu_lib
     m = StructuredMesh(3, k, n)
     g = DeformedGeometry(m, AMP, coefficient_modes(2))
