@@ -106,7 +106,6 @@ def measured_traffic(family):
     under profiles/ (FETCH_SIZE and WRITE_SIZE passes, calibrated on a plain copy),
     or None when none was taken on the kernel source as it is now."""
     import glob
-    import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
             t = line.split()
@@ -118,10 +117,22 @@ def measured_traffic(family):
             src = os.path.join(ROOT, kv.get("source", ""))
             if not os.path.isfile(src):
                 continue
-            if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("sha256"):
+            if source_digest(src) != kv.get("code_sha256"):
                 continue
             return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
     return None
+
+
+def source_digest(path):
+    """sha256 of a kernel source with its comments and blank lines removed, so
+    that editing a comment does not invalidate counters taken on the code."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = [ln.rstrip() for ln in text.splitlines() if ln.strip()]
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
 def kernel_bytes(P, dt_bytes):

@@ -514,6 +514,13 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
 // between the half-wavefronts gives the lower lane plane a and the upper lane
 // plane M-1-a, and the overlaps are then merged as in the one-lane kernel
 // (x across lanes, y through LDS, z through partial sums in the output).
+// A lane's merged plane is one cell's 128 contiguous bytes, 512 bytes from
+// the next lane's: written directly, every store instruction would touch 64
+// cache lines.  Instead each half-wavefront deposits its 32 planes in a
+// wavefront-private staging area (the last slice buffer, whose copy for the
+// next level is issued after the merge) and the wavefront stores them as
+// 16-byte chunks, 8 consecutive lanes per plane; the partial sums of the
+// level below are read back in the same orientation.
 //
 // A row of 32 patches touches 33 cells; the upper boundary cell of the mesh
 // (x = n-1) has no patch of its own and is assembled by the lane of patch
