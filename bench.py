@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--only-step", action="store_true", help="time the headline step only (for profilers)")
     ap.add_argument("--with-copy", action="store_true", help="with --only-step: add a plain copy kernel of known size")
     ap.add_argument("--only-pcg", action="store_true", help="run the Q7 32^3 MG-PCG solves only (for profilers)")
+    ap.add_argument("--only-deformed", action="store_true",
+                    help="run the deformed Q7 64^3 part only (training and the four solves; for profilers)")
     ap.add_argument("--step-config", default="q3", choices=["q3", "q7", "q7f32", "q3f32"],
                     help="with --only-step: which step to run (Q3 64^3 or Q7 32^3, FP64 or FP32)")
     return ap.parse_args()
@@ -186,6 +188,11 @@ def bench_pcg(fe):
     return out
 
 
+def bench_deformed_q7(fe):
+    """The end-to-end case: Q7 64^3 deformed, model trained on 40,000 patches of three Q7 32^3 meshes."""
+    return bench_deformed(fe, 7, 64, n_train=32, train_meshes=3, epochs=30, max_patches=40000)
+
+
 def bench_deformed(fe, k, n, n_train, train_meshes, epochs, with_solve=True, max_patches=None):
     """Deformed, variable-coefficient mesh: general apply rate; MLP trained on the patches of
     other generated meshes (other amplitudes and coefficient fields; at most max_patches,
@@ -317,6 +324,9 @@ def main():
     if args.only_pcg:
         print(json.dumps(bench_pcg(fe)))
         return
+    if args.only_deformed:
+        print(json.dumps(bench_deformed_q7(fe)))
+        return
     if args.only_step and args.step_config != "q3":
         deg, n = (7, 32) if args.step_config.startswith("q7") else (3, 64)
         dtype = torch.float32 if args.step_config.endswith("f32") else torch.float64
@@ -348,7 +358,7 @@ def main():
         log("deformed Q3 48^3 (apply, learned vs averaged factors)")
         deformed["q3_48cubed"] = bench_deformed(fe, 3, 48, n_train=24, train_meshes=2, epochs=30)
         log("deformed Q7 64^3 end-to-end solves")
-        deformed["q7_64cubed"] = bench_deformed(fe, 7, 64, n_train=32, train_meshes=3, epochs=30, max_patches=40000)
+        deformed["q7_64cubed"] = bench_deformed_q7(fe)
     cpu = None if args.no_cpu else cpu_baseline()
 
     # roofline entry for the dominant kernel of the headline step
