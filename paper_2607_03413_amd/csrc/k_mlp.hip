@@ -21,6 +21,7 @@
 namespace fe {
 
 constexpr int kIn = 64, kHid = 64, kOut = 12;
+static_assert(kIn <= 256 && kHid <= 256, "k_layer_bwd_w splits the batch over 256 / nin thread groups");
 constexpr int kW1 = kHid * kIn, kW2 = kHid * kHid, kW3 = kOut * kHid;
 constexpr int kParams = kW1 + kHid + kW2 + kHid + kW3 + kOut;   // 9100
 
@@ -323,20 +324,38 @@ __global__ void __launch_bounds__(256) k_layer_bwd_delta(const float* __restrict
 }
 
 // gW[o, i] = sum_b d[b, o] x[b, i]; gb[o] = sum_b d[b, o]  (one thread per weight, batch order fixed)
+// Weight and bias gradients of one layer: gW[o][i] = sum_b d[b][o] X[b][i],
+// gb[o] = sum_b d[b][o].  One block per output o; the batch is split over
+// Q = 256 / nin groups of nin threads (thread (q, i) sums rows b = q, q+Q, ...
+// for input i), and the Q partial sums are added in order through LDS.
+// (One thread per weight walking the whole batch left the GPU nearly empty.)
 __global__ void __launch_bounds__(256) k_layer_bwd_w(const float* __restrict__ d, const float* __restrict__ X,
                                                      float* __restrict__ gW, float* __restrict__ gb, int nb, int nin,
                                                      int nout) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid < nout * nin) {
-    const int o = gid / nin, i = gid - o * nin;
-    float s = 0.0f;
-    for (int b = 0; b < nb; ++b) s = fmaf(d[b * nout + o], X[b * nin + i], s);
-    gW[gid] = s;
-  } else if (gid < nout * nin + nout) {
-    const int o = gid - nout * nin;
-    float s = 0.0f;
-    for (int b = 0; b < nb; ++b) s += d[b * nout + o];
-    gb[o] = s;
+  __shared__ float part[256];
+  __shared__ float bpart[256];
+  const int o = blockIdx.x, t = threadIdx.x;
+  const int Q = 256 / nin, q = t / nin, i = t - q * nin;
+  float s = 0.0f, sb = 0.0f;
+  if (q < Q) {
+    for (int b = q; b < nb; b += Q) {
+      const float db = d[b * nout + o];
+      s = fmaf(db, X[b * nin + i], s);
+      sb += db;
+    }
+  }
+  part[t] = s;
+  bpart[t] = sb;
+  __syncthreads();
+  if (t < nin) {
+    float w = part[t];
+    for (int r = 1; r < Q; ++r) w += part[r * nin + t];
+    gW[o * nin + t] = w;
+  }
+  if (t == 0) {
+    float b = bpart[0];
+    for (int r = 1; r < Q; ++r) b += bpart[r * nin];
+    gb[o] = b;
   }
 }
 
@@ -415,15 +434,15 @@ static fe_status mlp_backward(const float* P, const float* X, const float* T, in
   *nparts = (int)nblk(n);
   hipLaunchKernelGGL(k_out_delta, dim3(nblk(n)), dim3(256), 0, s, w.y.as<float>(), T, w.d3.as<float>(), n,
                      2.0f / (float)n, part);
-  hipLaunchKernelGGL(k_layer_bwd_w, dim3(nblk(kW3 + kOut)), dim3(256), 0, s, w.d3.as<float>(), w.a2.as<float>(), gW3,
+  hipLaunchKernelGGL(k_layer_bwd_w, dim3(kOut), dim3(256), 0, s, w.d3.as<float>(), w.a2.as<float>(), gW3,
                      gb3, nb, kHid, kOut);
   hipLaunchKernelGGL(k_layer_bwd_delta, dim3(nblk(nb * kHid)), dim3(256), 0, s, w.d3.as<float>(), W3,
                      w.a2.as<float>(), w.d2.as<float>(), nb, kHid, kOut);
-  hipLaunchKernelGGL(k_layer_bwd_w, dim3(nblk(kW2 + kHid)), dim3(256), 0, s, w.d2.as<float>(), w.a1.as<float>(), gW2,
+  hipLaunchKernelGGL(k_layer_bwd_w, dim3(kHid), dim3(256), 0, s, w.d2.as<float>(), w.a1.as<float>(), gW2,
                      gb2, nb, kHid, kHid);
   hipLaunchKernelGGL(k_layer_bwd_delta, dim3(nblk(nb * kHid)), dim3(256), 0, s, w.d2.as<float>(), W2,
                      w.a1.as<float>(), w.d1.as<float>(), nb, kHid, kHid);
-  hipLaunchKernelGGL(k_layer_bwd_w, dim3(nblk(kW1 + kHid)), dim3(256), 0, s, w.d1.as<float>(), X, gW1, gb1, nb, kIn,
+  hipLaunchKernelGGL(k_layer_bwd_w, dim3(kHid), dim3(256), 0, s, w.d1.as<float>(), X, gW1, gb1, nb, kIn,
                      kHid);
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
