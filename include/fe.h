@@ -276,6 +276,17 @@ void fe_prof_enable(int enable);
 void fe_prof_reset(void);
 fe_status fe_prof_query(const char* name, int* count, double* total_ms);
 
+/* pcg_solve replays the preconditioner application z = M r (one V-cycle and
+ * its conversions, a fixed sequence of kernel launches per setup) as a HIP
+ * graph from its third application on: the first runs eagerly (it performs any
+ * first-use allocation), the second is captured.  pcg_solve runs on a stream
+ * of its own (capture needs a non-null stream), after the caller's stream has
+ * drained; the result is complete when it returns, as before.  enable = 0
+ * keeps every application eager (default 1).  Not used while per-kernel
+ * timing is on, or for the Jacobi smoother with an odd number of sweeps
+ * (whose sweeps alternate buffers between applications).  Process-wide. */
+void fe_set_graphs(int enable);
+
 /* Thread-local description of the last non-OK status. */
 const char* fe_last_error(void);
 

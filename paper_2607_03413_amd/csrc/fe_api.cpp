@@ -59,7 +59,12 @@ struct ProfRecord {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof;
+bool g_graphs_on = true;
 }  // namespace
+
+bool prof_enabled() { return g_prof_on; }
+bool graphs_enabled() { return g_graphs_on; }
+void set_graphs_enabled(bool on) { g_graphs_on = on; }
 
 ProfScope::ProfScope(const char* name, hipStream_t s) : slot(-1), stream(s) {
   if (!g_prof_on) return;
@@ -90,6 +95,7 @@ extern "C" {
 const char* fe_last_error(void) { return g_last_error.c_str(); }
 
 void fe_prof_enable(int enable) { g_prof_on = enable != 0; }
+void fe_set_graphs(int enable) { fe::set_graphs_enabled(enable != 0); }
 
 void fe_prof_reset(void) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

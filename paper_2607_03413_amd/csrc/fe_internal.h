@@ -34,6 +34,10 @@ fe_status fail(fe_status st, const std::string& msg);
 // ---------------------------------------------------------------- profiling
 // Kernel launches go through prof_begin/prof_end so that per-family durations
 // can be measured with events on the launch stream.
+bool prof_enabled();     // per-kernel event timing switched on (fe_prof_enable)
+bool graphs_enabled();   // the MG-PCG preconditioner may be replayed as a HIP graph (fe_set_graphs)
+void set_graphs_enabled(bool on);
+
 struct ProfScope {
   ProfScope(const char* name, hipStream_t s);
   ~ProfScope();

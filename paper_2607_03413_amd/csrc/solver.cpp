@@ -30,6 +30,25 @@ struct Solver {
   int inner = FE_F64;
   DeviceBuf r, z, pv, q, zf;  // finest-level FP64 PCG vectors
   DeviceBuf dscal;             // device doubles for reductions
+  // HIP graph of the preconditioner application (see apply_precond)
+  hipStream_t cs = nullptr;    // pcg_solve's own stream (capture needs a non-null stream)
+  int64_t gen = 0;             // bumped by every full setup
+  int64_t eager_gen = -1;      // generation of the last eager application
+  fe_pcg_opts eager_opts{};
+  hipGraphExec_t graph = nullptr;
+  int64_t graph_gen = -1;
+  fe_pcg_opts graph_opts{};
+  const void* graph_r = nullptr;
+  void* graph_z = nullptr;
+  void drop_graph() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+    graph_gen = -1;
+  }
+  ~Solver() {
+    drop_graph();
+    if (cs) (void)hipStreamDestroy(cs);
+  }
 };
 
 static bool same_setup(const fe_pcg_opts& a, const fe_pcg_opts& b) {
@@ -176,6 +195,8 @@ fe_status solver_setup(fe_problem* p, const fe_pcg_opts* o, hipStream_t s) {
   FE_HIP_CHECK(hipStreamSynchronize(s));
   S.opts = *o;
   S.ready = true;
+  ++S.gen;   // level data may have changed: a captured preconditioner is stale
+  S.drop_graph();
   return FE_OK;
 }
 
@@ -279,6 +300,58 @@ static fe_status precondition(fe_problem* p, const void* r, void* z, hipStream_t
   return launch_cast(F.len, F.e[di].p, dt, z, FE_F64, s);
 }
 
+// Options that shape the V-cycle's launch sequence (and the values baked into
+// its kernel arguments, together with the setup generation).
+static bool same_vcycle(const fe_pcg_opts& a, const fe_pcg_opts& b) {
+  return same_setup(a, b) && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post;
+}
+
+// z = M r, replayed as a HIP graph once the same application has run eagerly
+// with the current setup (the eager run performs any first-use allocation,
+// which capture would reject).  A V-cycle is a fixed sequence of launches on
+// fixed buffers with coefficients fixed at setup, and launch latency dominates
+// its coarse levels.  No fill or copy in it is a memset (those do not replay
+// reliably in graphs here).  Falls back to the eager path when capture fails.
+static fe_status apply_precond(fe_problem* p, const void* r, void* z, hipStream_t s) {
+  Solver& S = *p->solver;
+  const fe_pcg_opts& o = S.opts;
+  const bool safe = graphs_enabled() && !prof_enabled() && o.precond &&
+                    !(o.smoother == FE_SMOOTH_JACOBI && ((o.nu_pre & 1) || (o.nu_post & 1)));
+  if (!safe) {
+    S.drop_graph();
+    return precondition(p, r, z, s);
+  }
+  if (S.graph && S.graph_gen == S.gen && same_vcycle(S.graph_opts, o) && S.graph_r == r && S.graph_z == z) {
+    FE_HIP_CHECK(hipGraphLaunch(S.graph, s));
+    return FE_OK;
+  }
+  S.drop_graph();
+  if (S.eager_gen != S.gen || !same_vcycle(S.eager_opts, o)) {
+    S.eager_gen = S.gen;
+    S.eager_opts = o;
+    return precondition(p, r, z, s);
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return precondition(p, r, z, s);
+  const fe_status st = precondition(p, r, z, s);
+  const hipError_t ec = hipStreamEndCapture(s, &g);
+  hipGraphExec_t ex = nullptr;
+  if (st != FE_OK || ec != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    S.eager_gen = -1;   // capture again only after another eager run
+    return precondition(p, r, z, s);   // nothing captured was executed
+  }
+  (void)hipGraphDestroy(g);
+  S.graph = ex;
+  S.graph_gen = S.gen;
+  S.graph_opts = o;
+  S.graph_r = r;
+  S.graph_z = z;
+  FE_HIP_CHECK(hipGraphLaunch(ex, s));
+  return FE_OK;
+}
+
 }  // namespace fe
 
 using namespace fe;
@@ -356,9 +429,11 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
   hipStream_t s = (hipStream_t)stream;
   auto t0 = clk::now();
   FE_CHECK(solver_setup(p, o, s));
-  FE_HIP_CHECK(hipStreamSynchronize(s));
+  FE_HIP_CHECK(hipStreamSynchronize(s));   // the caller's stream has drained
   auto t1 = clk::now();
   Solver& S = *p->solver;
+  if (!S.cs) FE_HIP_CHECK(hipStreamCreateWithFlags(&S.cs, hipStreamNonBlocking));
+  s = S.cs;
   Level& F = p->levels.back();
   const int64_t n = F.len;
   void *r = S.r.p, *z = S.z.p, *pv = S.pv.p, *q = S.q.p;
@@ -383,7 +458,7 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
   if (!std::isfinite(nb2) || !std::isfinite(relres))
     result = fail(FE_EBREAKDOWN, "non-finite right-hand side or initial residual");
   if (result == FE_OK && relres > o->tol) {
-    FE_CHECK(precondition(p, r, z, s));
+    FE_CHECK(apply_precond(p, r, z, s));
     FE_CHECK(launch_cast(n, z, FE_F64, pv, FE_F64, s));
     double rho;
     FE_CHECK(dot_async(p, n, r, z, FE_F64, dev_scalar(p, 0), s));
@@ -415,7 +490,7 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
       }
       if (relres <= o->tol) break;
       if (o->flexible) FE_CHECK(read_scalar(p, 2, &rz_old, s));
-      FE_CHECK(precondition(p, r, z, s));
+      FE_CHECK(apply_precond(p, r, z, s));
       double rho_new;
       FE_CHECK(dot_async(p, n, r, z, FE_F64, dev_scalar(p, 0), s));
       FE_CHECK(read_scalar(p, 0, &rho_new, s));

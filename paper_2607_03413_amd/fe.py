@@ -94,6 +94,7 @@ _SIGS = {
     "fe_mlp_adam_step": (_i, [_vp, _vp, _d, _vp]),
     "fe_mlp_train": (_i, [_vp, _vp, _vp, _i, _i, _i, _d, ctypes.c_uint64, ctypes.POINTER(_d), _vp]),
     "fe_prof_enable": (None, [_i]),
+    "fe_set_graphs": (None, [_i]),
     "fe_prof_reset": (None, []),
     "fe_prof_query": (_i, [ctypes.c_char_p, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "fe_last_error": (ctypes.c_char_p, []),
@@ -307,6 +308,11 @@ class Problem:
         return {"status": STATUS.get(st, st), "iters": rep.iters, "converged": bool(rep.converged),
                 "relres": rep.relres, "energy0": rep.energy0, "energy": rep.energy, "t_setup": rep.t_setup,
                 "t_solve": rep.t_solve}
+
+
+def set_graphs(on=True):
+    """Replay the MG-PCG preconditioner as a HIP graph (default) or keep it eager."""
+    _lib.fe_set_graphs(1 if on else 0)
 
 
 def prof_enable(on=True):
