@@ -497,7 +497,7 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
 }
 
 // ---------------------------------------------------------------------------
-// Two lanes per patch (3D, k = 3, FP64).
+// Two lanes per patch (3D, k = 3, FP64 and FP32).
 //
 // One thread per patch needs the M^3 = 125 patch values in registers, which
 // in FP64 is the whole register file of a lane: one wavefront per SIMD and
@@ -734,7 +734,9 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
   // merge stores: lane (tq, tc) writes chunk tc of the plane of cell X0-1+q,
   // q = t*PPI + tq, t < NST; step t = NST, lanes tq = 0, writes the extra
   // boundary cell X0+31 = n-1.  Bit t of ownm: this block owns it.
-  constexpr int VPC = SP::VPC, PPI = 64 / NCH, NST = SP::NPX / PPI, TSTR = K2 + VPC;
+  // staging rows padded by one chunk in FP64 (conflict-free deposits); FP32 rows stay unpadded so
+  // that the staging area fits one slice buffer
+  constexpr int VPC = SP::VPC, PPI = 64 / NCH, NST = SP::NPX / PPI, TSTR = K2 + (sizeof(T) == 8 ? VPC : 0);
   static_assert(SP::NPX % PPI == 0 && (SP::NPX + 1) * TSTR * WY <= SLICE, "store staging must fit one slice buffer");
   typedef T vec_t __attribute__((ext_vector_type(VPC)));
   typedef __attribute__((address_space(3))) vec_t lds_vec_t;
@@ -1091,6 +1093,8 @@ fe_status launch_patch_fused(const fe_problem* p, int level, const void* r, void
     if (p->K == 4) return fused_typed<double, 4>(p, li, (const double*)r, (double*)z, p->coef64.as<double>(), s);
   } else {
     if (p->K == 3) return fused_typed<float, 3>(p, li, (const float*)r, (float*)z, p->coef32.as<float>(), s);
+    if (p->K == 4 && p->levels[li].n >= 2)
+      return split_typed<float, 4, FE_SPLIT_WY, FE_SPLIT_NB>(p, li, (const float*)r, (float*)z, p->coef32.as<float>(), s);
     if (p->K == 4) return fused_typed<float, 4>(p, li, (const float*)r, (float*)z, p->coef32.as<float>(), s);
   }
   return fail(FE_EUNSUPPORTED, "fused patch inverse: unsupported degree");
