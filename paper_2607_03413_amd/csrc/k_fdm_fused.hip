@@ -520,7 +520,8 @@ k_fdm_fused3(const T* __restrict__ r, T* __restrict__ z, const T* __restrict__ S
 // wavefront-private staging area (the last slice buffer, whose copy for the
 // next level is issued after the merge) and the wavefront stores them as
 // 16-byte chunks, 8 consecutive lanes per plane; the partial sums of the
-// level below are read back in the same orientation.
+// level below are read back in the same orientation (FP32: kept in LDS from
+// one level to the next instead, in the same orientation).
 //
 // A row of 32 patches touches 33 cells; the upper boundary cell of the mesh
 // (x = n-1) has no patch of its own and is assembled by the lane of patch
@@ -751,6 +752,16 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
   // wavefront-private staging area (padded rows: conflict-free deposits)
   __attribute__((address_space(3))) T* const stg =
       (__attribute__((address_space(3))) T*)buf(NBUF - 1) + wy * ((SP::NPX + 1) * TSTR);
+  // FP32: the partial sums of the upper planes wait for the next level in LDS
+  // (in the store orientation, wavefront-private) instead of a global write
+  // and read back; FP64 has no LDS left for them
+  constexpr bool PL = sizeof(T) == 4;
+  constexpr int PLN = PL ? WY * C * (NST + 1) * 64 * VPC : VPC;
+  __shared__ __attribute__((aligned(16))) T psum[PLN];
+  auto pslot = [&](int plane, int t) -> lds_vec_t* {   // partial plane 1..C, step t <= NST
+    return reinterpret_cast<lds_vec_t*>((__attribute__((address_space(3))) T*)psum +
+                                        (((wy * C + plane - 1) * (NST + 1) + t) * 64 + lane) * VPC);
+  };
 
   for (int e = tid; e < SP::ILS; e += 64 * WY) {
     const int h = e / (NE * M * M), rest = e - h * (NE * M * M), j = rest / (M * M), yx = rest - j * (M * M);
@@ -866,6 +877,16 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
     // at st_lo + t*PPI*K3 (layer vz-1) and st_hi + t*PPI*K3 (layer vz)
     T* const st_lo = z + (cell_xy - pi + tq + (int64_t)n * n * (vz - 1)) * K3 + tc * VPC;
     T* const st_hi = st_lo + (int64_t)n * n * K3;
+    // FP32: the partial sums this level completes, read before step 0 rewrites
+    // plane C with this level's own partial sums (one LDS slot per plane)
+    vec_t pold[PL ? C : 1][NST + 1];
+#pragma unroll
+    for (int pl = 0; pl < (PL ? C : 1); ++pl)
+#pragma unroll
+      for (int t = 0; t <= NST; ++t) {
+        pold[pl][t] = vec_t{};
+        if (PL && lo_ok && ((ownm >> t) & 1)) pold[pl][t] = *pslot(pl + 1, t);
+      }
 #pragma unroll
     for (int a = 0; a <= C; ++a) {
       if (a > 0) lds_barrier();   // the row above has read the previous plane
@@ -899,11 +920,15 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
         }
       }
       // partial sums of the level below, read in the store orientation
-      vec_t old[NST];
+      vec_t old[NST + 1];
 #pragma unroll
-      for (int t = 0; t < NST; ++t) {
+      for (int t = 0; t <= NST; ++t) {
         old[t] = vec_t{};   // defined on every path: no value is carried across levels
-        if (a < C && lo_ok && ((ownm >> t) & 1)) old[t] = *reinterpret_cast<const vec_t*>(st_lo + t * PPI * K3 + (a + 1) * K2);
+        if (PL) {
+          if (a < C) old[t] = pold[a < C ? a : 0][t];
+        } else if (t < NST) {
+          if (a < C && lo_ok && ((ownm >> t) & 1)) old[t] = *reinterpret_cast<const vec_t*>(st_lo + t * PPI * K3 + (a + 1) * K2);
+        }
       }
       lds_barrier();
       // the extra boundary cell, one value per lane (pi < K2, both halves):
@@ -959,18 +984,25 @@ k_fdm_fused3_split(const T* __restrict__ r, T* __restrict__ z, const T* __restri
         for (int t = 0; t < NST; ++t)
           if (lo_ok && ((ownm >> t) & 1)) *reinterpret_cast<vec_t*>(st_lo + t * PPI * K3 + (a + 1) * K2) = fetch(t) + old[t];
         if (lo_ok && ((ownm >> NST) & 1)) {
-          // boundary cell: added in memory (no load, so no wait behind the stores above)
           const vec_t v = fetch(NST);
           T* const e = st_lo + NST * PPI * K3 + (a + 1) * K2;
+          if (PL) {
+            *reinterpret_cast<vec_t*>(e) = v + old[NST];
+          } else {
+            // boundary cell: added in memory (no load, so no wait behind the stores above)
 #pragma unroll
-          for (int i = 0; i < VPC; ++i) unsafeAtomicAdd(e + i, v[i]);
+            for (int i = 0; i < VPC; ++i) unsafeAtomicAdd(e + i, v[i]);
+          }
         }
         __builtin_amdgcn_wave_barrier();
         // upper half: planes k-1-a of layer vz start as partial sums
         deposit(1);
 #pragma unroll
-        for (int t = 0; t <= NST; ++t)
-          if (hi_ok && ((ownm >> t) & 1)) *reinterpret_cast<vec_t*>(st_hi + t * PPI * K3 + (k - 1 - a) * K2) = fetch(t);
+        for (int t = 0; t <= NST; ++t) {
+          if (!(hi_ok && ((ownm >> t) & 1))) continue;
+          if (PL) *pslot(k - 1 - a, t) = fetch(t);
+          else *reinterpret_cast<vec_t*>(st_hi + t * PPI * K3 + (k - 1 - a) * K2) = fetch(t);
+        }
       } else {
         // the middle plane: the vertex plane of both layers
         deposit(0);
