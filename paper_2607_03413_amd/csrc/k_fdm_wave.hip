@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS)
                                                         const T* __restrict__ eig, const T* __restrict__ il,
                                                         T scale, int n) {
   using P = WavePatch<K>;
-  constexpr int k = P::k, M = P::M, M2 = P::M2, M3 = P::M3;
+  constexpr int M = P::M, M2 = P::M2, M3 = P::M3;
   constexpr int K3 = K * K * K;
   constexpr bool EO = !PER_PATCH;
   __shared__ T t[M3];
