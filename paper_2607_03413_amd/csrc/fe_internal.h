@@ -163,6 +163,12 @@ fe_status launch_cheb_update(int64_t n, double a, const void* v, double c, void*
                              fe_dtype dt, hipStream_t s);
 fe_status launch_patch_inverse(const fe_problem* p, int level, const void* r, void* z, void* scratch,
                                fe_dtype dt, int factors, hipStream_t s);
+// v = P r followed by the Chebyshev step of launch_cheb_update (w = a v + c w;
+// e = w or e += w).  On 3D meshes served by the two-pass inverse the step runs
+// inside the summing pass and v is neither written nor read (v may be null
+// there); elsewhere v receives P r (it may alias w) and the update follows.
+fe_status launch_patch_cheb(const fe_problem* p, int level, const void* r, void* v, void* scratch, fe_dtype dt,
+                            int factors, double a, double c, void* w, void* e, int e_zero, hipStream_t s);
 size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt);
 fe_status launch_prolongate_add(const fe_problem* p, int fine_level, const void* ec, void* ef,
                                 fe_dtype dt, hipStream_t s);

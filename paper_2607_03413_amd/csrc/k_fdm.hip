@@ -253,6 +253,17 @@ __global__ void __launch_bounds__(256) k_fdm_patch3(const T* __restrict__ r, T* 
 // so no thread divides by n.  No load is branched around (a branch per load
 // made each one wait for its data before the next was issued): an absent
 // patch is read at W[0] and added times 0, an exact 0.
+// Optional Chebyshev step fused into the summing pass (CH != 0), in place of
+// storing v = P r: w = a v (CH 1, 2) or w = a v + c w (CH 3), then e = w (CH 1)
+// or e += w (CH 2, 3), the same arithmetic as the separate update kernel.  It
+// saves writing v and reading it back, two full vectors per smoothing step.
+template <typename T>
+struct ChebArgs {
+  T a, c;
+  T* w;
+  T* e;
+};
+
 template <int K>
 struct SumSlots {
   static constexpr int K3 = K * K * K;
@@ -260,8 +271,20 @@ struct SumSlots {
   static constexpr int THREADS = CPB * K3;
 };
 
-template <typename T, int K>
-__global__ void __launch_bounds__(SumSlots<K>::THREADS) k_fdm_sum_slots3(const T* __restrict__ W, T* __restrict__ z, int n) {
+template <typename T, int CH>
+__device__ __forceinline__ void cheb_store(const ChebArgs<T>& ch, T* z, int64_t i, T v, T wo, T eo) {
+  if (CH == 0) {
+    z[i] = v;
+  } else {
+    const T wn = CH == 3 ? fma(ch.a, v, ch.c * wo) : ch.a * v;
+    ch.w[i] = wn;
+    ch.e[i] = CH == 1 ? wn : eo + wn;
+  }
+}
+
+template <typename T, int K, int CH>
+__global__ void __launch_bounds__(SumSlots<K>::THREADS) k_fdm_sum_slots3(const T* __restrict__ W, T* __restrict__ z, int n,
+                                                                         ChebArgs<T> ch) {
   constexpr int k = K - 1;
   constexpr int k3 = k * k * k;
   constexpr int K3 = K * K * K;
@@ -270,9 +293,12 @@ __global__ void __launch_bounds__(SumSlots<K>::THREADS) k_fdm_sum_slots3(const T
   if (cx >= n) return;
   const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
   const int nv = n - 1;
-  T* const out = z + ((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc;
+  const int64_t oi = ((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc;
+  // the Chebyshev operands are fetched ahead of the patch values
+  const T wo = CH == 3 ? ch.w[oi] : T(0);
+  const T eo = CH >= 2 ? ch.e[oi] : T(0);
   if (nv < 1) {   // no patch at all (and possibly no scratch)
-    *out = T(0);
+    cheb_store<T, CH>(ch, z, oi, T(0), wo, eo);
     return;
   }
   T s = T(0);
@@ -295,7 +321,7 @@ __global__ void __launch_bounds__(SumSlots<K>::THREADS) k_fdm_sum_slots3(const T
       }
     }
   }
-  *out = s;
+  cheb_store<T, CH>(ch, z, oi, s, wo, eo);
 }
 
 template <typename T, int K, bool PER_PATCH>
@@ -419,8 +445,9 @@ __global__ void __launch_bounds__(256) k_fdm_sum2(const T* __restrict__ W, T* __
 // i > 0; candidates outside 1..n-1 or not containing the node contribute 0.
 // The sum runs over (z, y, x) patch candidates in ascending vertex order,
 // which depends only on the node: all copies receive identical values.
-template <typename T, int K>
-__global__ void __launch_bounds__((K * K + 63) / 64 * 64) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n) {
+template <typename T, int K, int CH>
+__global__ void __launch_bounds__((K * K + 63) / 64 * 64) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n,
+                                                                       ChebArgs<T> ch) {
   constexpr int k = K - 1;
   constexpr int M = 2 * k - 1;
   constexpr int MP = M * M * M;
@@ -447,11 +474,19 @@ __global__ void __launch_bounds__((K * K + 63) / 64 * 64) k_fdm_sum_pm3(const T*
   // patch (cx-1, cy-1, cz-1) and the strides to its neighbours along y and z
   const int64_t p000 = (int64_t)(cx - 1) + (int64_t)nv * ((cy - 1) + (int64_t)nv * (cz - 1));
   const int64_t sy = nv, sz = (int64_t)nv * nv;
-  T* const zc = z + ((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * NL;
+  // entry (ix, iy, iz) of the cell sits at oc + iz K^2 (lanes past K^2 use entry 0)
+  const int64_t oc = ((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * NL + (act ? loc : 0);
+  // the Chebyshev operands are fetched ahead of the patch values
+  T wo[K], eo[K];
+#pragma unroll
+  for (int iz = 0; iz < K; ++iz) {
+    wo[iz] = CH == 3 ? ch.w[oc + iz * K * K] : T(0);
+    eo[iz] = CH >= 2 ? ch.e[oc + iz * K * K] : T(0);
+  }
   if (nv < 1) {   // no patch at all (and possibly no scratch)
 #pragma unroll
     for (int iz = 0; iz < K; ++iz)
-      if (act) zc[iz * K * K + loc] = T(0);
+      if (act) cheb_store<T, CH>(ch, z, oc + iz * K * K, T(0), wo[iz], eo[iz]);
     return;
   }
   // Patches in ascending vertex order (z, then y, then x), as every copy of a
@@ -487,7 +522,7 @@ __global__ void __launch_bounds__((K * K + 63) / 64 * 64) k_fdm_sum_pm3(const T*
   }
   if (act) {
 #pragma unroll
-    for (int iz = 0; iz < K; ++iz) zc[iz * K * K + loc] = acc[iz];
+    for (int iz = 0; iz < K; ++iz) cheb_store<T, CH>(ch, z, oc + iz * K * K, acc[iz], wo[iz], eo[iz]);
   }
 }
 
@@ -508,9 +543,25 @@ size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt) {
   return (size_t)(np * mp) * (dt == FE_F64 ? 8 : 4);
 }
 
+template <typename T, int K, int CH>
+static fe_status launch_sum3(const fe_problem* p, const Level& L, const T* W, T* z, bool per_patch, const ChebArgs<T>& ch,
+                             hipStream_t s) {
+  ProfScope ps2("fdm_sum", s);
+  if (patch_wave_supported(p, per_patch))   // patch-major solutions
+    hipLaunchKernelGGL((k_fdm_sum_pm3<T, K, CH>), dim3((unsigned)L.n, (unsigned)L.n, (unsigned)L.n), dim3((K * K + 63) / 64 * 64), 0,
+                       s, W, z, L.n, ch);
+  else                                      // slot-split solutions
+    hipLaunchKernelGGL((k_fdm_sum_slots3<T, K, CH>),
+                       dim3((unsigned)((L.n + SumSlots<K>::CPB - 1) / SumSlots<K>::CPB), (unsigned)L.n, (unsigned)L.n),
+                       dim3(SumSlots<K>::THREADS), 0, s, W, z, L.n, ch);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+// ch_mode 0: z = P r; 1..3: the fused Chebyshev step of ChebArgs (3D only)
 template <typename T, int K>
 static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T* z, T* W, const T* eig,
-                             bool per_patch, T scale, hipStream_t s) {
+                             bool per_patch, T scale, int ch_mode, const ChebArgs<T>& ch, hipStream_t s) {
   constexpr int M = 2 * (K - 1) - 1;
   const int64_t nv = L.n - 1;
   if (p->dim == 3) {
@@ -529,13 +580,12 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
         hipLaunchKernelGGL((k_fdm_patch3<T, K, false>), dim3(nb), dim3(THREADS), 0, s, r, W, eig, scale, L.n, segs);
       FE_HIP_CHECK(hipGetLastError());
     }
-    ProfScope ps2("fdm_sum", s);
-    if (patch_wave_supported(p, per_patch))   // patch-major solutions
-      hipLaunchKernelGGL((k_fdm_sum_pm3<T, K>), dim3((unsigned)L.n, (unsigned)L.n, (unsigned)L.n), dim3((K * K + 63) / 64 * 64), 0, s, W, z, L.n);
-    else                                      // slot-split solutions
-      hipLaunchKernelGGL((k_fdm_sum_slots3<T, K>),
-                         dim3((unsigned)((L.n + SumSlots<K>::CPB - 1) / SumSlots<K>::CPB), (unsigned)L.n, (unsigned)L.n),
-                         dim3(SumSlots<K>::THREADS), 0, s, W, z, L.n);
+    switch (ch_mode) {
+      case 1: return launch_sum3<T, K, 1>(p, L, W, z, per_patch, ch, s);
+      case 2: return launch_sum3<T, K, 2>(p, L, W, z, per_patch, ch, s);
+      case 3: return launch_sum3<T, K, 3>(p, L, W, z, per_patch, ch, s);
+      default: return launch_sum3<T, K, 0>(p, L, W, z, per_patch, ch, s);
+    }
   } else {
     const int64_t np = nv * nv;
     if (np > 0) {
@@ -556,11 +606,20 @@ static fe_status patch_typed(const fe_problem* p, const Level& L, const T* r, T*
   return FE_OK;
 }
 
-fe_status launch_patch_inverse(const fe_problem* p, int level, const void* r, void* z, void* scratch,
-                               fe_dtype dt, int factors, hipStream_t s) {
+// Chebyshev mode of the summing pass for w = a v + c w with e = w (e_zero) or
+// e += w; 0 where it runs as a separate update (c != 0 with e = w does not occur
+// in a smoothing sweep).
+template <typename T>
+static int cheb_mode(T c, int e_zero) {
+  if (c == T(0)) return e_zero ? 1 : 2;
+  return e_zero ? 0 : 3;
+}
+
+static fe_status patch_dispatch(const fe_problem* p, int level, const void* r, void* z, void* scratch, fe_dtype dt,
+                                int factors, bool cheb, double a, double c, void* w, void* e, int e_zero,
+                                hipStream_t s) {
   const Level& L = level_of(p, level);
   const bool per_patch = factors != 0;
-  if (fused_patch_supported(p, per_patch)) return launch_patch_fused(p, level, r, z, dt, s);
   const double scale = per_patch ? 1.0 : std::pow(L.h, 2 - p->dim);
   const int li = level < 0 ? (int)p->levels.size() - 1 : level;
   const void* eig;
@@ -573,11 +632,32 @@ fe_status launch_patch_inverse(const fe_problem* p, int level, const void* r, vo
                        : (const void*)(p->coef32.as<float>() + p->co.off_S);
   }
   if (dt == FE_F64) {
+    const ChebArgs<double> ch{a, c, (double*)w, (double*)e};
+    const int mode = cheb ? cheb_mode(ch.c, e_zero) : 0;
     FE_DISPATCH_K(p->K, return (patch_typed<double, KK>(p, L, (const double*)r, (double*)z, (double*)scratch,
-                                                        (const double*)eig, per_patch, scale, s)));
+                                                        (const double*)eig, per_patch, scale, mode, ch, s)));
   }
+  const ChebArgs<float> ch{(float)a, (float)c, (float*)w, (float*)e};
+  const int mode = cheb ? cheb_mode(ch.c, e_zero) : 0;
   FE_DISPATCH_K(p->K, return (patch_typed<float, KK>(p, L, (const float*)r, (float*)z, (float*)scratch,
-                                                     (const float*)eig, per_patch, (float)scale, s)));
+                                                     (const float*)eig, per_patch, (float)scale, mode, ch, s)));
+}
+
+fe_status launch_patch_inverse(const fe_problem* p, int level, const void* r, void* z, void* scratch,
+                               fe_dtype dt, int factors, hipStream_t s) {
+  if (fused_patch_supported(p, factors != 0)) return launch_patch_fused(p, level, r, z, dt, s);
+  return patch_dispatch(p, level, r, z, scratch, dt, factors, false, 0.0, 0.0, nullptr, nullptr, 0, s);
+}
+
+fe_status launch_patch_cheb(const fe_problem* p, int level, const void* r, void* v, void* scratch, fe_dtype dt,
+                            int factors, double a, double c, void* w, void* e, int e_zero, hipStream_t s) {
+  const bool c_zero = dt == FE_F64 ? c == 0.0 : (float)c == 0.0f;
+  const bool fusable = p->dim == 3 && !fused_patch_supported(p, factors != 0) && (c_zero || !e_zero);
+  if (!fusable) {
+    FE_CHECK(launch_patch_inverse(p, level, r, v, scratch, dt, factors, s));
+    return launch_cheb_update(level_of(p, level).len, a, v, c, w, e, e_zero, dt, s);
+  }
+  return patch_dispatch(p, level, r, nullptr, scratch, dt, factors, true, a, c, w, e, e_zero, s);
 }
 
 }  // namespace fe

@@ -72,6 +72,15 @@ static fe_status patch_apply(fe_problem* p, int l, const void* r, void* z, fe_dt
   return launch_patch_inverse(p, l, r, z, scr.p, dt, factors, s);
 }
 
+// v = P r, then w = a v + c w and e = w (e_zero) or e += w
+static fe_status patch_cheb(fe_problem* p, int l, const void* r, void* v, fe_dtype dt, int factors, double a, double c,
+                            void* w, void* e, int e_zero, hipStream_t s) {
+  Level& L = p->levels[l];
+  DeviceBuf& scr = L.fdm_scratch[dt == FE_F64 ? 0 : 1];
+  FE_CHECK(scr.alloc(patch_scratch_bytes(p, l, dt)));
+  return launch_patch_cheb(p, l, r, v, scr.p, dt, factors, a, c, w, e, e_zero, s);
+}
+
 // lambda_max of P A on level l by CG-Lanczos from a fixed start vector; P is the
 // patch inverse (smoother = FE_SMOOTH_CHEB_FDM) or the Jacobi preconditioner
 // G D^{-1} G^T = S_bar(K_cell D_cell^{-1} .) (smoother = FE_SMOOTH_JACOBI).
@@ -240,13 +249,12 @@ static fe_status cheb_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe_d
     if (z) FE_CHECK(launch_cast(n, b, dt, t, dt, s));
     else FE_CHECK(launch_apply_ep(p, l, e, t, -1.0, 1.0, b, dt, s));
     // w = P t / theta; e += w
-    FE_CHECK(patch_apply(p, l, t, w, dt, o.factors, s));
-    FE_CHECK(launch_cheb_update(n, 1.0 / theta, w, 0.0, w, e, z ? 1 : 0, dt, s));
+    FE_CHECK(patch_cheb(p, l, t, w, dt, o.factors, 1.0 / theta, 0.0, w, e, z ? 1 : 0, s));
     for (int it = 1; it < o.cheb_degree; ++it) {
       FE_CHECK(launch_apply_ep(p, l, w, t, -1.0, 1.0, t, dt, s));   // t -= A w
       const double rho_new = 1.0 / (2.0 * sigma - rho);
-      FE_CHECK(patch_apply(p, l, t, v, dt, o.factors, s));         // v = P t (primal)
-      FE_CHECK(launch_cheb_update(n, 2.0 * rho_new / delta, v, rho_new * rho, w, e, 0, dt, s));
+      // v = P t (primal), w = 2 rho_new / delta v + rho_new rho w, e += w
+      FE_CHECK(patch_cheb(p, l, t, v, dt, o.factors, 2.0 * rho_new / delta, rho_new * rho, w, e, 0, s));
       rho = rho_new;
     }
   }
