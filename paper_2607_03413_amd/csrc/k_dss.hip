@@ -79,6 +79,84 @@ __global__ void __launch_bounds__(256) k_gather(const T* __restrict__ xg, T* __r
   xc[e] = xg[gidx];
 }
 
+// 3D, cell-wise: the thread of a cell-wise entry (cell c, local index i) finds
+// the node's other copies by index arithmetic.  Along one axis, the other copy
+// is (c-1, k) for i = 0 and (c+1, 0) for i = k when that cell exists (w = 1);
+// otherwise it is the entry itself, with w = 0.
+template <int K>
+__device__ __forceinline__ void other_copy(int c, int i, int n, int& co, int& io, int& w) {
+  constexpr int k = K - 1;
+  const bool lo = i == 0 && c > 0, hi = i == k && c < n - 1;
+  co = lo ? c - 1 : (hi ? c + 1 : c);
+  io = lo ? k : (hi ? 0 : i);
+  w = (lo || hi) ? 1 : 0;
+}
+
+// Sum of all copies of the node of entry (cx, cy, cz; ix, iy, iz), grouped as
+// in the cascade: x pairs, then the y pair of x sums, then the z pair (each
+// pair sum is the same whichever copy forms it).  All eight loads are issued:
+// an absent partner re-reads the entry's own copy and is added times 0, an
+// exact 0, so that no load waits behind a branch.  kappa = number of copies.
+template <typename T, int K>
+__device__ __forceinline__ T node_sum3(const T* __restrict__ v, int cx, int cy, int cz, int ix, int iy, int iz, int n,
+                                       int& kappa) {
+  constexpr int64_t K3 = K * K * K;
+  int xo, jx, wx, yo, jy, wy, zo, jz, wz;
+  other_copy<K>(cx, ix, n, xo, jx, wx);
+  other_copy<K>(cy, iy, n, yo, jy, wy);
+  other_copy<K>(cz, iz, n, zo, jz, wz);
+  auto at = [&](int a, int b, int c, int i, int j, int l) {
+    return v[((int64_t)a + (int64_t)n * (b + (int64_t)n * c)) * K3 + i + K * (j + K * l)];
+  };
+  const T v000 = at(cx, cy, cz, ix, iy, iz), v100 = at(xo, cy, cz, jx, iy, iz);
+  const T v010 = at(cx, yo, cz, ix, jy, iz), v110 = at(xo, yo, cz, jx, jy, iz);
+  const T v001 = at(cx, cy, zo, ix, iy, jz), v101 = at(xo, cy, zo, jx, iy, jz);
+  const T v011 = at(cx, yo, zo, ix, jy, jz), v111 = at(xo, yo, zo, jx, jy, jz);
+  const T tx = T(wx), ty = T(wy), tz = T(wz);
+  const T x00 = fma(v100, tx, v000), x10 = fma(v110, tx, v010);
+  const T x01 = fma(v101, tx, v001), x11 = fma(v111, tx, v011);
+  const T y0 = fma(x10, ty, x00), y1 = fma(x11, ty, x01);
+  kappa = (1 + wx) * (1 + wy) * (1 + wz);
+  return fma(y1, tz, y0);
+}
+
+// Whole cells per block for the cell-wise passes (at least one wavefront).
+template <int K>
+struct CellBlock {
+  static constexpr int K3 = K * K * K;
+  static constexpr int CPB = K3 >= 64 ? 1 : 64 / K3;
+  static constexpr int THREADS = CPB * K3;
+};
+
+// Partial sums of (G^T r)_g^2, 3D: every node is counted once, by its copy of
+// highest cell (local index < k, or the last cell along that axis).
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_assembled_norm2_cells(const T* __restrict__ v, int n, int64_t len,
+                                                               double* __restrict__ part) {
+  constexpr int k = K - 1;
+  constexpr int K3 = K * K * K;
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cell = e / K3;
+    const int loc = (int)(e - cell * K3);
+    int cx, cy, cz;
+    cell_coords3<false>(cell, n, cx, cy, cz);
+    const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+    const bool owned = (ix < k || cx == n - 1) && (iy < k || cy == n - 1) && (iz < k || cz == n - 1);
+    int kappa;
+    const double s = (double)node_sum3<T, K>(v, cx, cy, cz, ix, iy, iz, n, kappa);
+    acc += owned ? s * s : 0.0;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 // Partial sums of (G^T r)_g^2 over the nodes, one value per block (FP64).
 template <typename T, int K, int DIM>
 __global__ void __launch_bounds__(256) k_assembled_norm2_partial(const T* __restrict__ v, int n,
@@ -126,6 +204,22 @@ __global__ void __launch_bounds__(256) k_average_convert(const double* __restric
       for (int sx = 0; sx < ax.cnt; ++sx) out[copy_addr<K, DIM>(ax, ay, az, sx, sy, sz, n)] = s;
 }
 
+// k_average_convert, 3D and cell-wise: a thread per cell-wise entry forms its
+// node's average and writes its own entry, so the writes are whole cache lines
+// (grid: x-groups of whole cells, n, n).
+template <typename T, int K>
+__global__ void __launch_bounds__(CellBlock<K>::THREADS) k_average_convert3(const double* __restrict__ r,
+                                                                           T* __restrict__ out, int n) {
+  constexpr int K3 = K * K * K;
+  const int cl = threadIdx.x / K3, loc = threadIdx.x - cl * K3;
+  const int cx = blockIdx.x * CellBlock<K>::CPB + cl, cy = blockIdx.y, cz = blockIdx.z;
+  if (cx >= n) return;
+  const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+  int kappa;
+  const double s = node_sum3<double, K>(r, cx, cy, cz, ix, iy, iz, n, kappa);
+  out[((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc] = (T)(s * (1.0 / kappa));
+}
+
 template <int K>
 static fe_status average_convert_typed(const fe_problem* p, int level, const double* r, void* out, fe_dtype dt,
                                        hipStream_t s) {
@@ -134,12 +228,16 @@ static fe_status average_convert_typed(const fe_problem* p, int level, const dou
   const int64_t nn = p->dim == 3 ? N * N * N : N * N;
   const unsigned nb = (unsigned)((nn + 255) / 256);
   ProfScope ps("average_convert", s);
-  if (dt == FE_F32) {
-    if (p->dim == 3) hipLaunchKernelGGL((k_average_convert<float, K, 3>), dim3(nb), dim3(256), 0, s, r, (float*)out, L.n, nn);
-    else hipLaunchKernelGGL((k_average_convert<float, K, 2>), dim3(nb), dim3(256), 0, s, r, (float*)out, L.n, nn);
+  if (p->dim == 3) {
+    const dim3 grid((unsigned)((L.n + CellBlock<K>::CPB - 1) / CellBlock<K>::CPB), (unsigned)L.n, (unsigned)L.n);
+    if (dt == FE_F32)
+      hipLaunchKernelGGL((k_average_convert3<float, K>), grid, dim3(CellBlock<K>::THREADS), 0, s, r, (float*)out, L.n);
+    else
+      hipLaunchKernelGGL((k_average_convert3<double, K>), grid, dim3(CellBlock<K>::THREADS), 0, s, r, (double*)out, L.n);
+  } else if (dt == FE_F32) {
+    hipLaunchKernelGGL((k_average_convert<float, K, 2>), dim3(nb), dim3(256), 0, s, r, (float*)out, L.n, nn);
   } else {
-    if (p->dim == 3) hipLaunchKernelGGL((k_average_convert<double, K, 3>), dim3(nb), dim3(256), 0, s, r, (double*)out, L.n, nn);
-    else hipLaunchKernelGGL((k_average_convert<double, K, 2>), dim3(nb), dim3(256), 0, s, r, (double*)out, L.n, nn);
+    hipLaunchKernelGGL((k_average_convert<double, K, 2>), dim3(nb), dim3(256), 0, s, r, (double*)out, L.n, nn);
   }
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
@@ -196,13 +294,16 @@ static fe_status gather_typed(const fe_problem* p, const Level& L, const T* xg, 
 template <typename T, int K>
 static fe_status norm2_typed(const fe_problem* p, const Level& L, const T* v, double* dev_out, hipStream_t s) {
   const int64_t nn = n_nodes_of(p, L);
-  int nparts = (int)std::min<int64_t>(1024, (nn + 255) / 256);
   double* part = p->red_scratch.as<double>();
   ProfScope ps("assembled_norm2", s);
-  if (p->dim == 3)
-    hipLaunchKernelGGL((k_assembled_norm2_partial<T, K, 3>), dim3(nparts), dim3(256), 0, s, v, L.n, nn, part);
-  else
+  int nparts;
+  if (p->dim == 3) {
+    nparts = (int)std::min<int64_t>(1024, (L.len + 255) / 256);
+    hipLaunchKernelGGL((k_assembled_norm2_cells<T, K>), dim3(nparts), dim3(256), 0, s, v, L.n, L.len, part);
+  } else {
+    nparts = (int)std::min<int64_t>(1024, (nn + 255) / 256);
     hipLaunchKernelGGL((k_assembled_norm2_partial<T, K, 2>), dim3(nparts), dim3(256), 0, s, v, L.n, nn, part);
+  }
   FE_HIP_CHECK(hipGetLastError());
   return finish_reduction(p, nparts, dev_out, s);
 }

@@ -52,6 +52,20 @@ def test_gather_assemble_bit_exact(gpu_lib, dim, k, n):
 
 @pytest.mark.parametrize("dim,k,n", CASES)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_assembled_norm2_exact_on_integers(gpu_lib, dim, k, n, dtype):
+    """||G^T v||^2 (Sec. 2.1: G^T sums the cell copies): on integer-valued copies
+    every sum and square is exact, so the value is the oracle's to the bit; each
+    node counted once, whichever copy counts it."""
+    fe = gpu_lib
+    m = StructuredMesh(dim, k, n)
+    P = fe.Problem(dim, k, n, bc=0)
+    v = integer_valued(m.n_cellwise, seed=103)
+    expect = float(np.sum(m.assemble(v) ** 2))
+    assert P.assembled_norm2(dev(v, dtype)) == expect
+
+
+@pytest.mark.parametrize("dim,k,n", CASES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_dss_bit_exact_on_integers(gpu_lib, dim, k, n, dtype):
     fe = gpu_lib
     m = StructuredMesh(dim, k, n)
