@@ -180,10 +180,15 @@ fe_status launch_jacobi_update(const fe_problem* p, int level, const void* b, co
 fe_status launch_rhs(const fe_problem* p, void* b, hipStream_t s);
 // blas-1 on cell-wise vectors (n entries)
 fe_status launch_axpby(int64_t n, double a, const void* x, double b, void* y, fe_dtype dt, hipStream_t s);
+// y = a x + b y, y FP64, x FP64 or FP32 (xdt)
+fe_status launch_axpby_x(int64_t n, double a, const void* x, fe_dtype xdt, double b, double* y, hipStream_t s);
 fe_status launch_cast(int64_t n, const void* src, fe_dtype st, void* dst, fe_dtype dtt, hipStream_t s);
 fe_status launch_fill(int64_t n, void* x, double v, fe_dtype dt, hipStream_t s);
 fe_status dot_async(const fe_problem* p, int64_t n, const void* a, const void* b, fe_dtype dt,
                     double* dev_out, hipStream_t s);
+// <a, b> with a FP64 and b FP64 or FP32 (bdt), into *dev_out (device)
+fe_status dot_async_x(const fe_problem* p, int64_t n, const double* a, const void* b, fe_dtype bdt, double* dev_out,
+                      hipStream_t s);
 fe_status assembled_norm2_async(const fe_problem* p, int level, const void* r, fe_dtype dt,
                                 double* dev_out, hipStream_t s);
 fe_status launch_coarse_solve(const fe_problem* p, const void* b0, void* e0, fe_dtype dt, hipStream_t s);

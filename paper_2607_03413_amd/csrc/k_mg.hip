@@ -212,6 +212,13 @@ __global__ void __launch_bounds__(256) k_axpby(int64_t n, T a, const T* __restri
   if (e < n) y[e] = b == T(0) ? a * x[e] : fma(a, x[e], b * y[e]);
 }
 
+// y = a x + b y with an FP32 x (converted exactly) and FP64 y
+__global__ void __launch_bounds__(256) k_axpby_f32x(int64_t n, double a, const float* __restrict__ x, double b,
+                                                    double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = b == 0.0 ? a * (double)x[e] : fma(a, (double)x[e], b * y[e]);
+}
+
 // Chebyshev step: w = a v + c w (v may alias w), then e = w or e += w.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cheb_update(int64_t n, T a, const T* v, T c, T* w, T* __restrict__ e,
@@ -235,8 +242,8 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, T* __restrict__ x, T v)
   if (e < n) x[e] = v;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const T* __restrict__ a, const T* __restrict__ b,
+template <typename T, typename TB = T>
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const T* __restrict__ a, const TB* __restrict__ b,
                                                      double* __restrict__ part) {
   double acc = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
@@ -451,6 +458,14 @@ fe_status launch_axpby(int64_t n, double a, const void* x, double b, void* y, fe
   return FE_OK;
 }
 
+fe_status launch_axpby_x(int64_t n, double a, const void* x, fe_dtype xdt, double b, double* y, hipStream_t s) {
+  if (xdt == FE_F64) return launch_axpby(n, a, x, b, y, FE_F64, s);
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_axpby_f32x, dim3(nb), dim3(256), 0, s, n, a, (const float*)x, b, y);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
 fe_status launch_cheb_update(int64_t n, double a, const void* v, double c, void* w, void* e, int e_zero,
                              fe_dtype dt, hipStream_t s) {
   const unsigned nb = (unsigned)((n + 255) / 256);
@@ -503,6 +518,17 @@ fe_status dot_async(const fe_problem* p, int64_t n, const void* a, const void* b
   else
     hipLaunchKernelGGL(k_dot_partial<float>, dim3(nparts), dim3(256), 0, s, n, (const float*)a, (const float*)b,
                        p->red_scratch.as<double>());
+  FE_HIP_CHECK(hipGetLastError());
+  return finish_reduction(p, nparts, dev_out, s);
+}
+
+fe_status dot_async_x(const fe_problem* p, int64_t n, const double* a, const void* b, fe_dtype bdt, double* dev_out,
+                      hipStream_t s) {
+  if (bdt == FE_F64) return dot_async(p, n, a, b, FE_F64, dev_out, s);
+  const int nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  ProfScope ps("dot", s);
+  hipLaunchKernelGGL((k_dot_partial<double, float>), dim3(nparts), dim3(256), 0, s, n, a, (const float*)b,
+                     p->red_scratch.as<double>());
   FE_HIP_CHECK(hipGetLastError());
   return finish_reduction(p, nparts, dev_out, s);
 }

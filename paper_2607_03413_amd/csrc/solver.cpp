@@ -233,25 +233,25 @@ static fe_status jacobi_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe
 
 // Chebyshev semi-iteration on [lmax/ratio, lmax] preconditioned by the patch inverse.
 // Buffers: e = iterate, b = rhs, t = residual (dual), w = direction (primal),
-// v = A w (dual), and the patch output reuses v's role through y = w's update.
+// v = P t (primal) where the step does not run inside the patch inverse.
 static fe_status cheb_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe_dtype dt, hipStream_t s) {
   Level& L = p->levels[l];
   const int di = dt == FE_F64 ? 0 : 1;
   const fe_pcg_opts& o = p->solver->opts;
   const double lmax = 1.2 * L.lmax, lmin = lmax / o.cheb_ratio;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
-  const int64_t n = L.len;
   void *e = L.e[di].p, *b = L.b[di].p, *t = L.t[di].p, *w = L.w[di].p, *v = L.v[di].p;
   for (int sw = 0; sw < sweeps; ++sw) {
     const bool z = u_zero && sw == 0;
     double rho = 1.0 / sigma;
-    // t = b - A e (the residual fused into the operator's store)
-    if (z) FE_CHECK(launch_cast(n, b, dt, t, dt, s));
-    else FE_CHECK(launch_apply_ep(p, l, e, t, -1.0, 1.0, b, dt, s));
+    // t = b - A e (the residual fused into the operator's store); from a zero
+    // start the residual is b itself and is read in place
+    if (!z) FE_CHECK(launch_apply_ep(p, l, e, t, -1.0, 1.0, b, dt, s));
     // w = P t / theta; e += w
-    FE_CHECK(patch_cheb(p, l, t, w, dt, o.factors, 1.0 / theta, 0.0, w, e, z ? 1 : 0, s));
+    FE_CHECK(patch_cheb(p, l, z ? b : t, w, dt, o.factors, 1.0 / theta, 0.0, w, e, z ? 1 : 0, s));
     for (int it = 1; it < o.cheb_degree; ++it) {
-      FE_CHECK(launch_apply_ep(p, l, w, t, -1.0, 1.0, t, dt, s));   // t -= A w
+      // t -= A w (t = b - A w after a zero start: nothing was copied into t)
+      FE_CHECK(launch_apply_ep(p, l, w, t, -1.0, 1.0, z && it == 1 ? b : t, dt, s));
       const double rho_new = 1.0 / (2.0 * sigma - rho);
       // v = P t (primal), w = 2 rho_new / delta v + rho_new rho w, e += w
       FE_CHECK(patch_cheb(p, l, t, v, dt, o.factors, 2.0 * rho_new / delta, rho_new * rho, w, e, 0, s));
@@ -291,7 +291,7 @@ fe_status solver_vcycle(fe_problem* p, const fe_pcg_opts* o, fe_dtype dt, hipStr
   return vcycle_level(p, (int)p->levels.size() - 1, dt, s);
 }
 
-// z = M r (finest level): r, z FP64
+// z = M r (finest level): r, z FP64 (with a preconditioner, z may be null)
 static fe_status precondition(fe_problem* p, const void* r, void* z, hipStream_t s) {
   Solver& S = *p->solver;
   Level& F = p->levels.back();
@@ -305,7 +305,8 @@ static fe_status precondition(fe_problem* p, const void* r, void* z, hipStream_t
   if (dt == FE_F32) FE_CHECK(launch_average_convert(p, -1, (const double*)r, F.b[di].p, dt, s));
   else FE_CHECK(launch_cast(F.len, r, FE_F64, F.b[di].p, dt, s));
   FE_CHECK(vcycle_level(p, (int)p->levels.size() - 1, dt, s));
-  return launch_cast(F.len, F.e[di].p, dt, z, FE_F64, s);
+  // z null: the result stays in the finest level's iterate, in the inner precision
+  return z ? launch_cast(F.len, F.e[di].p, dt, z, FE_F64, s) : FE_OK;
 }
 
 // Options that shape the V-cycle's launch sequence (and the values baked into
@@ -445,6 +446,19 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
   Level& F = p->levels.back();
   const int64_t n = F.len;
   void *r = S.r.p, *z = S.z.p, *pv = S.pv.p, *q = S.q.p;
+  // z = M r: with a preconditioner the V-cycle's result is read where it lies,
+  // the finest level's iterate in the inner precision (FP32 values enter the
+  // FP64 dot products and direction update exactly), so no FP64 copy is made.
+  // It stays intact until the next application, past the flexible <r, z_old>.
+  const void* zc = z;
+  fe_dtype zdt = FE_F64;
+  auto precond = [&]() -> fe_status {
+    if (!S.opts.precond) return apply_precond(p, r, z, s);
+    FE_CHECK(apply_precond(p, r, nullptr, s));
+    zdt = (fe_dtype)S.opts.inner;
+    zc = F.e[zdt == FE_F64 ? 0 : 1].p;
+    return FE_OK;
+  };
   double nb2, rr2;
   // Dirichlet problem: the residual lives in the dual of the interior space, so
   // the boundary copies of b are masked out (they carry no equation).
@@ -466,10 +480,10 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
   if (!std::isfinite(nb2) || !std::isfinite(relres))
     result = fail(FE_EBREAKDOWN, "non-finite right-hand side or initial residual");
   if (result == FE_OK && relres > o->tol) {
-    FE_CHECK(apply_precond(p, r, z, s));
-    FE_CHECK(launch_cast(n, z, FE_F64, pv, FE_F64, s));
+    FE_CHECK(precond());
+    FE_CHECK(launch_cast(n, zc, zdt, pv, FE_F64, s));
     double rho;
-    FE_CHECK(dot_async(p, n, r, z, FE_F64, dev_scalar(p, 0), s));
+    FE_CHECK(dot_async_x(p, n, (const double*)r, zc, zdt, dev_scalar(p, 0), s));
     FE_CHECK(read_scalar(p, 0, &rho, s));
     R.energy0 = rho;
     R.energy = rho;
@@ -489,7 +503,7 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
       FE_CHECK(launch_axpby(n, -alpha, q, 1.0, r, FE_F64, s));
       FE_CHECK(assembled_norm2_async(p, -1, r, FE_F64, dev_scalar(p, 1), s));
       double rz_old = 0.0;
-      if (o->flexible) FE_CHECK(dot_async(p, n, r, z, FE_F64, dev_scalar(p, 2), s));
+      if (o->flexible) FE_CHECK(dot_async_x(p, n, (const double*)r, zc, zdt, dev_scalar(p, 2), s));
       FE_CHECK(read_scalar(p, 1, &rr2, s));
       relres = std::sqrt(rr2) / nb;
       if (!std::isfinite(relres)) {
@@ -498,9 +512,9 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
       }
       if (relres <= o->tol) break;
       if (o->flexible) FE_CHECK(read_scalar(p, 2, &rz_old, s));
-      FE_CHECK(apply_precond(p, r, z, s));
+      FE_CHECK(precond());
       double rho_new;
-      FE_CHECK(dot_async(p, n, r, z, FE_F64, dev_scalar(p, 0), s));
+      FE_CHECK(dot_async_x(p, n, (const double*)r, zc, zdt, dev_scalar(p, 0), s));
       FE_CHECK(read_scalar(p, 0, &rho_new, s));
       R.energy = rho_new;
       if (!(rho_new > 0.0)) {
@@ -508,7 +522,7 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
         break;
       }
       const double beta = o->flexible ? (rho_new - rz_old) / rho : rho_new / rho;
-      FE_CHECK(launch_axpby(n, 1.0, z, beta, pv, FE_F64, s));
+      FE_CHECK(launch_axpby_x(n, 1.0, zc, zdt, beta, (double*)pv, s));
       rho = rho_new;
     }
     if (result == FE_OK && relres > o->tol) result = fail(FE_ENOTCONV, "maximum number of iterations reached");
