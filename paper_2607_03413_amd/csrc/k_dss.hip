@@ -92,26 +92,35 @@ __device__ __forceinline__ void other_copy(int c, int i, int n, int& co, int& io
   w = (lo || hi) ? 1 : 0;
 }
 
-// Sum of all copies of the node of entry (cx, cy, cz; ix, iy, iz), grouped as
-// in the cascade: x pairs, then the y pair of x sums, then the z pair (each
-// pair sum is the same whichever copy forms it).  All eight loads are issued:
-// an absent partner re-reads the entry's own copy and is added times 0, an
-// exact 0, so that no load waits behind a branch.  kappa = number of copies.
+// Sum of all copies of the node of entry (cx, cy, cz; ix, iy, iz), whose own
+// copy is at *p, grouped as in the cascade: x pairs, then the y pair of x
+// sums, then the z pair (each pair sum is the same whichever copy forms it).
+// The other copies are 32-bit offsets from p.  The loads are not branched
+// around per lane: an absent partner re-reads the entry's own copy and is
+// added times 0, an exact 0, so that no load waits behind a divergent branch.
+// kappa = number of copies.
 template <typename T, int K>
-__device__ __forceinline__ T node_sum3(const T* __restrict__ v, int cx, int cy, int cz, int ix, int iy, int iz, int n,
+__device__ __forceinline__ T node_sum3(const T* __restrict__ p, int cx, int cy, int cz, int ix, int iy, int iz, int n,
                                        int& kappa) {
-  constexpr int64_t K3 = K * K * K;
+  constexpr int K3 = K * K * K;
   int xo, jx, wx, yo, jy, wy, zo, jz, wz;
   other_copy<K>(cx, ix, n, xo, jx, wx);
   other_copy<K>(cy, iy, n, yo, jy, wy);
   other_copy<K>(cz, iz, n, zo, jz, wz);
-  auto at = [&](int a, int b, int c, int i, int j, int l) {
-    return v[((int64_t)a + (int64_t)n * (b + (int64_t)n * c)) * K3 + i + K * (j + K * l)];
-  };
-  const T v000 = at(cx, cy, cz, ix, iy, iz), v100 = at(xo, cy, cz, jx, iy, iz);
-  const T v010 = at(cx, yo, cz, ix, jy, iz), v110 = at(xo, yo, cz, jx, jy, iz);
-  const T v001 = at(cx, cy, zo, ix, iy, jz), v101 = at(xo, cy, zo, jx, iy, jz);
-  const T v011 = at(cx, yo, zo, ix, jy, jz), v111 = at(xo, yo, zo, jx, jy, jz);
+  const int dx = (xo - cx) * K3 + (jx - ix);
+  const int dy = (yo - cy) * (n * K3) + (jy - iy) * K;
+  const int dz = (zo - cz) * (n * n * K3) + (jz - iz) * (K * K);
+  // the z partners are loaded only where a lane of the wavefront has one (a
+  // uniform branch taken before any load: at Q7 a wavefront is one z-plane of
+  // a cell, and two planes in eight have z partners)
+  T v000, v100, v010, v110, v001, v101, v011, v111;
+  if (__ballot(wz) != 0) {
+    v000 = p[0]; v100 = p[dx]; v010 = p[dy]; v110 = p[dx + dy];
+    v001 = p[dz]; v101 = p[dx + dz]; v011 = p[dy + dz]; v111 = p[dx + dy + dz];
+  } else {
+    v000 = p[0]; v100 = p[dx]; v010 = p[dy]; v110 = p[dx + dy];
+    v001 = v000; v101 = v100; v011 = v010; v111 = v110;
+  }
   const T tx = T(wx), ty = T(wy), tz = T(wz);
   const T x00 = fma(v100, tx, v000), x10 = fma(v110, tx, v010);
   const T x01 = fma(v101, tx, v001), x11 = fma(v111, tx, v011);
@@ -129,23 +138,26 @@ struct CellBlock {
 };
 
 // Partial sums of (G^T r)_g^2, 3D: every node is counted once, by its copy of
-// highest cell (local index < k, or the last cell along that axis).
+// highest cell (local index < k, or the last cell along that axis).  A block
+// takes whole x-rows of cells (contiguous n K^3 values; cy, cz uniform).
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_assembled_norm2_cells(const T* __restrict__ v, int n, int64_t len,
+__global__ void __launch_bounds__(256) k_assembled_norm2_cells(const T* __restrict__ v, int n,
                                                                double* __restrict__ part) {
   constexpr int k = K - 1;
   constexpr int K3 = K * K * K;
+  const int nrow = n * n, rowlen = n * K3;
   double acc = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cell = e / K3;
-    const int loc = (int)(e - cell * K3);
-    int cx, cy, cz;
-    cell_coords3<false>(cell, n, cx, cy, cz);
-    const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
-    const bool owned = (ix < k || cx == n - 1) && (iy < k || cy == n - 1) && (iz < k || cz == n - 1);
-    int kappa;
-    const double s = (double)node_sum3<T, K>(v, cx, cy, cz, ix, iy, iz, n, kappa);
-    acc += owned ? s * s : 0.0;
+  for (int row = blockIdx.x; row < nrow; row += gridDim.x) {
+    const int cz = row / n, cy = row - cz * n;
+    const T* vr = v + (int64_t)row * rowlen;
+    for (int j = threadIdx.x; j < rowlen; j += blockDim.x) {
+      const int cx = j / K3, loc = j - cx * K3;
+      const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+      const bool owned = (ix < k || cx == n - 1) && (iy < k || cy == n - 1) && (iz < k || cz == n - 1);
+      int kappa;
+      const double s = (double)node_sum3<T, K>(vr + j, cx, cy, cz, ix, iy, iz, n, kappa);
+      acc += owned ? s * s : 0.0;
+    }
   }
   __shared__ double red[256];
   red[threadIdx.x] = acc;
@@ -215,9 +227,10 @@ __global__ void __launch_bounds__(CellBlock<K>::THREADS) k_average_convert3(cons
   const int cx = blockIdx.x * CellBlock<K>::CPB + cl, cy = blockIdx.y, cz = blockIdx.z;
   if (cx >= n) return;
   const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
+  const int64_t own = ((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc;
   int kappa;
-  const double s = node_sum3<double, K>(r, cx, cy, cz, ix, iy, iz, n, kappa);
-  out[((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc] = (T)(s * (1.0 / kappa));
+  const double s = node_sum3<double, K>(r + own, cx, cy, cz, ix, iy, iz, n, kappa);
+  out[own] = (T)(s * (1.0 / kappa));
 }
 
 template <int K>
@@ -298,8 +311,8 @@ static fe_status norm2_typed(const fe_problem* p, const Level& L, const T* v, do
   ProfScope ps("assembled_norm2", s);
   int nparts;
   if (p->dim == 3) {
-    nparts = (int)std::min<int64_t>(1024, (L.len + 255) / 256);
-    hipLaunchKernelGGL((k_assembled_norm2_cells<T, K>), dim3(nparts), dim3(256), 0, s, v, L.n, L.len, part);
+    nparts = (int)std::min<int64_t>(1024, (int64_t)L.n * L.n);
+    hipLaunchKernelGGL((k_assembled_norm2_cells<T, K>), dim3(nparts), dim3(256), 0, s, v, L.n, part);
   } else {
     nparts = (int)std::min<int64_t>(1024, (nn + 255) / 256);
     hipLaunchKernelGGL((k_assembled_norm2_partial<T, K, 2>), dim3(nparts), dim3(256), 0, s, v, L.n, nn, part);
