@@ -23,6 +23,8 @@
 // With the exact Cartesian factors the mirror symmetry of the two-cell patch
 // is used: every eigenvector is even or odd about the middle node, so a
 // line costs (c+1)^2 + c^2 instead of m^2 FMAs (c = k-1).
+#include <type_traits>
+
 #include "fe_internal.h"
 #include "kernel_common.h"
 
@@ -164,10 +166,11 @@ __device__ __forceinline__ AxisCopies wave_axis_copies(int a) {
 // otherwise (EO) the even/odd halves of the Cartesian S and the eigenvalues,
 // and il the level's table of scale / (l_x + l_y + l_z) in the same mode order.
 template <typename T, int K, bool PER_PATCH>
-// (per-patch FP32: at least 5 wavefronts per SIMD, measured faster than the
-// 128 VGPRs the compiler takes by itself for the residual loads)
+// (FP32: at least 5 wavefronts per SIMD with per-patch factors, measured
+// faster than the 128 VGPRs the compiler takes by itself for the residual
+// loads; at least 4 with the Cartesian factors, which would otherwise take 134)
 __global__ void __launch_bounds__(WavePatch<K>::THREADS)
-    __attribute__((amdgpu_waves_per_eu(PER_PATCH && sizeof(T) == 4 ? 5 : 1))) k_fdm_patch3_wave(const T* __restrict__ r, T* __restrict__ W,
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (PER_PATCH ? 5 : 4) : 1))) k_fdm_patch3_wave(const T* __restrict__ r, T* __restrict__ W,
                                                         const T* __restrict__ eig, const T* __restrict__ il,
                                                         T scale, int n) {
   using P = WavePatch<K>;
@@ -218,25 +221,33 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS)
       // copy reads it twice and weights the second by 0): a load behind a
       // lane-dependent branch waits for its data before the next is issued.
       // fma(b, 1, a) rounds as a + b, so the sums are those of the copies.
+      // Only the wavefront holding the row y = k-1 (the patch's middle, a cell
+      // face) has second copies along y; the others skip those loads (a
+      // uniform branch around the whole assembly, taken before any load).
       const T wx = cx.cnt == 2 ? T(1) : T(0), wy = cy.cnt == 2 ? T(1) : T(0);
+      auto assemble = [&](auto two_y) {
+        constexpr int NY = decltype(two_y)::value ? 2 : 1;
 #pragma unroll
-      for (int z = 0; z < M; ++z) {
-        const AxisCopies cz = wave_axis_copies<K>(z);   // compile-time after unrolling
-        T zs = T(0);
+        for (int z = 0; z < M; ++z) {
+          const AxisCopies cz = wave_axis_copies<K>(z);   // compile-time after unrolling
+          T zs = T(0);
 #pragma unroll
-        for (int sz = 0; sz < 2; ++sz) {
-          if (sz >= cz.cnt) break;
-          T ys = T(0);
+          for (int sz = 0; sz < 2; ++sz) {
+            if (sz >= cz.cnt) break;
+            T ys = T(0);
 #pragma unroll
-          for (int sy = 0; sy < 2; ++sy) {
-            const T* cb = rc + cz.c[sz] * sz_cells + cy.c[sy] * sy_cells + K * (cy.i[sy] + K * cz.i[sz]);
-            const T xs = fma(cb[cx.c[1] * K3 + cx.i[1]], wx, cb[cx.c[0] * K3 + cx.i[0]]);
-            ys = sy == 0 ? xs : fma(xs, wy, ys);
+            for (int sy = 0; sy < NY; ++sy) {
+              const T* cb = rc + cz.c[sz] * sz_cells + cy.c[sy] * sy_cells + K * (cy.i[sy] + K * cz.i[sz]);
+              const T xs = fma(cb[cx.c[1] * K3 + cx.i[1]], wx, cb[cx.c[0] * K3 + cx.i[0]]);
+              ys = sy == 0 ? xs : fma(xs, wy, ys);
+            }
+            zs = sz == 0 ? ys : zs + ys;
           }
-          zs = sz == 0 ? ys : zs + ys;
+          v[z] = zs;
         }
-        v[z] = zs;
-      }
+      };
+      if (__ballot(cy.cnt == 2) != 0) assemble(std::true_type{});
+      else assemble(std::false_type{});
       if (PER_PATCH) line_apply_lds<T, M, MS, true>(fz, v, w);
       else line_apply<T, M, EO, true>(Sz, v, w);
 #pragma unroll
