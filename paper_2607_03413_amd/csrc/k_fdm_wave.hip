@@ -214,19 +214,32 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS)
   {
     const int l = lane;
     if (l < M2) {
-      const int x = l % M, y = l / M;
+      // Only pencils on the patch's middle cross (x = k-1 or y = k-1, a cell
+      // face) have second copies along x or y.  They take the first lanes
+      // (the column x = k-1, then the rest of the row y = k-1), the other
+      // pencils follow in row order, so that the wavefronts without any such
+      // pencil load one copy per node (a uniform branch around the whole
+      // assembly, taken before any load).
+      constexpr int C = P::C;
+      int x, y;
+      if (l < M) {
+        x = C; y = l;
+      } else if (l < 2 * M - 1) {
+        const int q = l - M;
+        x = q < C ? q : q + 1; y = C;
+      } else {
+        const int q = l - (2 * M - 1), yy = q / (M - 1), xx = q - yy * (M - 1);
+        x = xx < C ? xx : xx + 1; y = yy < C ? yy : yy + 1;
+      }
       const AxisCopies cx = wave_axis_copies<K>(x), cy = wave_axis_copies<K>(y);
       T v[M], w[M];
-      // Both copies along x and y are loaded in every lane (a node with one
-      // copy reads it twice and weights the second by 0): a load behind a
-      // lane-dependent branch waits for its data before the next is issued.
-      // fma(b, 1, a) rounds as a + b, so the sums are those of the copies.
-      // Only the wavefront holding the row y = k-1 (the patch's middle, a cell
-      // face) has second copies along y; the others skip those loads (a
-      // uniform branch around the whole assembly, taken before any load).
+      // On the cross both copies along x and y are loaded in every lane (a
+      // node with one copy reads it twice and weights the second by 0): a load
+      // behind a lane-dependent branch waits for its data before the next is
+      // issued.  fma(b, 1, a) rounds as a + b, so the sums are those of the copies.
       const T wx = cx.cnt == 2 ? T(1) : T(0), wy = cy.cnt == 2 ? T(1) : T(0);
-      auto assemble = [&](auto two_y) {
-        constexpr int NY = decltype(two_y)::value ? 2 : 1;
+      auto assemble = [&](auto cross) {
+        constexpr int NC = decltype(cross)::value ? 2 : 1;
 #pragma unroll
         for (int z = 0; z < M; ++z) {
           const AxisCopies cz = wave_axis_copies<K>(z);   // compile-time after unrolling
@@ -236,9 +249,10 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS)
             if (sz >= cz.cnt) break;
             T ys = T(0);
 #pragma unroll
-            for (int sy = 0; sy < NY; ++sy) {
+            for (int sy = 0; sy < NC; ++sy) {
               const T* cb = rc + cz.c[sz] * sz_cells + cy.c[sy] * sy_cells + K * (cy.i[sy] + K * cz.i[sz]);
-              const T xs = fma(cb[cx.c[1] * K3 + cx.i[1]], wx, cb[cx.c[0] * K3 + cx.i[0]]);
+              const T xs = NC == 2 ? fma(cb[cx.c[1] * K3 + cx.i[1]], wx, cb[cx.c[0] * K3 + cx.i[0]])
+                                   : cb[cx.c[0] * K3 + cx.i[0]];
               ys = sy == 0 ? xs : fma(xs, wy, ys);
             }
             zs = sz == 0 ? ys : zs + ys;
@@ -246,7 +260,7 @@ __global__ void __launch_bounds__(WavePatch<K>::THREADS)
           v[z] = zs;
         }
       };
-      if (__ballot(cy.cnt == 2) != 0) assemble(std::true_type{});
+      if (__ballot(cx.cnt == 2 || cy.cnt == 2) != 0) assemble(std::true_type{});
       else assemble(std::false_type{});
       if (PER_PATCH) line_apply_lds<T, M, MS, true>(fz, v, w);
       else line_apply<T, M, EO, true>(Sz, v, w);
