@@ -117,7 +117,8 @@ def test_apply_fp64_and_fp32(gpu_lib, dim, k, n, bc):
 
 
 @pytest.mark.parametrize("dim,k,n", [(2, 2, 16), (2, 3, 5), (3, 1, 4), (3, 2, 3), (3, 3, 4), (3, 3, 5),
-                                     (3, 2, 9), (3, 3, 8), (3, 3, 1), (3, 4, 3), (3, 7, 3), (3, 8, 2)])
+                                     (3, 2, 9), (3, 3, 8), (3, 3, 1), (3, 4, 3), (3, 5, 3), (3, 6, 3),
+                                     (3, 7, 3), (3, 8, 2)])
 def test_patch_inverse_fp64_fp32_and_continuity(gpu_lib, dim, k, n):
     fe = gpu_lib
     m = StructuredMesh(dim, k, n)

@@ -98,11 +98,11 @@ def test_jacobi_vcycle_equals_classical(gpu_lib, k, n, inner):
     assert relerr(host(e), expect) < tol
 
 
-@pytest.mark.parametrize("k,n", [(2, 4), (3, 4), (7, 2), (1, 4), (5, 2)])
+@pytest.mark.parametrize("k,n", [(2, 4), (3, 4), (7, 2), (1, 4), (5, 2), (6, 2)])
 @pytest.mark.parametrize("inner", [0, 1])
 def test_chebyshev_fdm_vcycle_equals_classical(gpu_lib, k, n, inner):
     """Covers every summing pass that carries the Chebyshev step: k = 1 (slot
-    layout), k = 5, 7 (patch-major), and k = 2, 3 with the fused inverse plus a
+    layout), k = 5, 6, 7 (patch-major), and k = 2, 3 with the fused inverse plus a
     separate update."""
     fe = gpu_lib
     h = Hierarchy(3, k, n)
