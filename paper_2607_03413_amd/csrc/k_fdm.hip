@@ -445,8 +445,12 @@ __global__ void __launch_bounds__(256) k_fdm_sum2(const T* __restrict__ W, T* __
 // i > 0; candidates outside 1..n-1 or not containing the node contribute 0.
 // The sum runs over (z, y, x) patch candidates in ascending vertex order,
 // which depends only on the node: all copies receive identical values.
+// (FP32: at most 4 wavefronts per SIMD asked for, so that the scheduler keeps
+// every load in flight; aiming at more, it waited for each z node's loads
+// before issuing the next once the Chebyshev operands were live as well)
 template <typename T, int K, int CH>
-__global__ void __launch_bounds__((K * K + 63) / 64 * 64) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n,
+__global__ void __launch_bounds__((K * K + 63) / 64 * 64)
+    __attribute__((amdgpu_waves_per_eu(1, sizeof(T) == 4 ? 4 : 8))) k_fdm_sum_pm3(const T* __restrict__ W, T* __restrict__ z, int n,
                                                                        ChebArgs<T> ch) {
   constexpr int k = K - 1;
   constexpr int M = 2 * k - 1;
