@@ -294,13 +294,14 @@ __global__ void __launch_bounds__(SumSlots<K>::THREADS) k_fdm_sum_slots3(const T
   const int ix = loc % K, iy = (loc / K) % K, iz = loc / (K * K);
   const int nv = n - 1;
   const int64_t oi = ((int64_t)cx + (int64_t)n * (cy + (int64_t)n * cz)) * K3 + loc;
-  // the Chebyshev operands are fetched ahead of the patch values
-  const T wo = CH == 3 ? ch.w[oi] : T(0);
-  const T eo = CH >= 2 ? ch.e[oi] : T(0);
   if (nv < 1) {   // no patch at all (and possibly no scratch)
-    cheb_store<T, CH>(ch, z, oi, T(0), wo, eo);
+    cheb_store<T, CH>(ch, z, oi, T(0), CH == 3 ? ch.w[oi] : T(0), CH >= 2 ? ch.e[oi] : T(0));
     return;
   }
+  // the Chebyshev operands are fetched ahead of the patch values (after the
+  // branch above: used there, they were waited for before the patch loads)
+  const T wo = CH == 3 ? ch.w[oi] : T(0);
+  const T eo = CH >= 2 ? ch.e[oi] : T(0);
   T s = T(0);
 #pragma unroll
   for (int bz = 0; bz < 2; ++bz) {
