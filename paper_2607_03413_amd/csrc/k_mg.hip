@@ -40,13 +40,16 @@ __global__ void __launch_bounds__(256) k_prolong3(const T* __restrict__ ec, T* _
   T* lb0 = sb + c * CS;
   T* lb1 = sb + (CPB + c) * CS;
   T v[K], u[K], w[K];
-  if (active) {
-    const T* src = ec + par * K3 + p0 + K * p1;
+  // Every lane loads (a lane past the last parent reads parent 0, in bounds,
+  // and discards it): a load behind a lane-dependent branch waits for its data
+  // before the next one is issued.
+  {
+    const T* src = ec + (active ? par : 0) * K3 + p0 + K * p1;
 #pragma unroll
-    for (int iz = 0; iz < K; ++iz) v[iz] = src[iz * K * K];
-  } else {
-#pragma unroll
-    for (int iz = 0; iz < K; ++iz) v[iz] = T(0);
+    for (int iz = 0; iz < K; ++iz) {
+      const T x = src[iz * K * K];
+      v[iz] = active ? x : T(0);
+    }
   }
   for (int bz = 0; bz < 2; ++bz) {
     pencil_mv<T, K>(bz ? P1 : P0, v, u);
@@ -70,11 +73,16 @@ __global__ void __launch_bounds__(256) k_prolong3(const T* __restrict__ ec, T* _
       for (int j = 0; j < K; ++j) u[j] = lb[p1 * PS + p0 * RS + j];
       for (int bx = 0; bx < 2; ++bx) {
         pencil_mv<T, K>(bx ? P1 : P0, u, w);
-        if (active) {
-          const int64_t child = (2 * px + bx) + (int64_t)nf * ((2 * py + by) + (int64_t)nf * (2 * pz + bz));
-          T* dst = ef + child * K3 + K * p0 + K * K * p1;
+        // loaded in every lane (px = py = pz = 0 past the last parent: in
+        // bounds), stored by the active ones only
+        const int64_t child = (2 * px + bx) + (int64_t)nf * ((2 * py + by) + (int64_t)nf * (2 * pz + bz));
+        T* dst = ef + child * K3 + K * p0 + K * K * p1;
+        T old[K];
 #pragma unroll
-          for (int ix = 0; ix < K; ++ix) dst[ix] += w[ix];
+        for (int ix = 0; ix < K; ++ix) old[ix] = dst[ix];
+        if (active) {
+#pragma unroll
+          for (int ix = 0; ix < K; ++ix) dst[ix] = old[ix] + w[ix];
         }
       }
     }
@@ -108,14 +116,21 @@ __global__ void __launch_bounds__(256) k_restrict3(const T* __restrict__ bf, con
 #pragma unroll
       for (int i = 0; i < K; ++i) acc[i] = T(0);
       for (int bx = 0; bx < 2; ++bx) {
-        if (active) {
-          const int64_t child = (2 * px + bx) + (int64_t)nf * ((2 * py + by) + (int64_t)nf * (2 * pz + bz));
-          const int64_t off = child * K3 + K * p0 + K * K * p1;
+        // every lane loads (px = py = pz = 0 past the last parent: in bounds,
+        // discarded), and the branch on vf is uniform and comes before any load
+        const int64_t child = (2 * px + bx) + (int64_t)nf * ((2 * py + by) + (int64_t)nf * (2 * pz + bz));
+        const int64_t off = child * K3 + K * p0 + K * K * p1;
+        T bv[K], vv[K];
+        if (vf) {
 #pragma unroll
-          for (int ix = 0; ix < K; ++ix) r[ix] = vf ? bf[off + ix] - vf[off + ix] : bf[off + ix];
+          for (int ix = 0; ix < K; ++ix) { bv[ix] = bf[off + ix]; vv[ix] = vf[off + ix]; }
+#pragma unroll
+          for (int ix = 0; ix < K; ++ix) r[ix] = active ? bv[ix] - vv[ix] : T(0);
         } else {
 #pragma unroll
-          for (int ix = 0; ix < K; ++ix) r[ix] = T(0);
+          for (int ix = 0; ix < K; ++ix) bv[ix] = bf[off + ix];
+#pragma unroll
+          for (int ix = 0; ix < K; ++ix) r[ix] = active ? bv[ix] : T(0);
         }
         pencil_mtv<T, K>(bx ? P1 : P0, r, s);
 #pragma unroll
