@@ -134,6 +134,15 @@ fe_status patch_fdm_inverse(const fe_problem* prob, const void* r_cell, void* z_
 fe_status patch_fdm_inverse_level(const fe_problem* prob, int level, const void* r_cell, void* z_cell,
                                   fe_dtype dt, int factors, void* stream);
 
+/* Set-up of patch_fdm_inverse on (level, dt, factors): the per-patch factors
+ * of `factors` (deformed mesh: quadrature inner products, eigensolves, model
+ * inference) and, where the two-pass kernels serve the problem (k >= 4, k = 1,
+ * d = 2, per-patch factors), the patch-solution scratch in dtype dt, owned by
+ * the problem until fe_problem_destroy.  Synchronous.  patch_fdm_inverse on a
+ * prepared (level, dt, factors) allocates nothing; on an unprepared one it
+ * runs this set-up first.  pcg_solve prepares every level it smooths on. */
+fe_status fe_patch_prepare(fe_problem* prob, int level, fe_dtype dt, int factors, void* stream);
+
 /* Sec. 3.1 Algorithm 2: e_fine += (P_b1 x P_b2 x P_b3) e_coarse on every
  * child, level `fine_level` >= 1.  Continuous in, continuous out (lemma on
  * commutativity of prolongation). */
@@ -178,7 +187,8 @@ typedef struct {
   int smoother;            /* fe_smoother */
   int cheb_degree;         /* Chebyshev degree (smoother = 1) */
   double cheb_ratio;       /* interval [lmax/ratio, lmax] */
-  double cheb_lmax;        /* > 0: use this lambda_max estimate on every level (tests) */
+  double cheb_lmax;        /* > 0: lmax, the top of the interval, on every level, taken as given;
+                              0: per level 1.2 x a 15-step Lanczos estimate of lambda_max(P A) */
   double omega;            /* Jacobi relaxation (smoother = 0); 0: per level 4/(3 lambda_max(D^-1 A)) */
   int inner;               /* fe_dtype of the V-cycle (FE_F32: FP32 preconditioner) */
   int factors;             /* patch factors for smoother = 1 (see patch_fdm_inverse) */

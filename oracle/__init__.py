@@ -19,6 +19,6 @@ patch      vertex patches, dense patch matrices and their inverses
 geometry   deformed Q_k geometry, coefficient field, general element matrices
 kron       Kronecker form of the Cartesian operator and its exact solver
 multigrid  assembled hierarchy, classical smoothers, V-cycle, PCG
-sepfit     best separable (Kronecker-sum) fit of patch matrices
-mlp        reference MLP forward / manual backward / Adam step
+sepfit     averaged-geometry separable factors and the separable patch inverse
+learned    patch features, best-fit targets, reference MLP forward / manual backward / Adam step
 """

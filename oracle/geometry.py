@@ -13,7 +13,7 @@ under a smooth deformation, with a variable coefficient:
 * element matrix A_K,ij = sum_q w_q kappa(x_q) det(J_q)
   (J_q^{-T} grad phi_i) . (J_q^{-T} grad phi_j) with a (k+1)^3 Gauss rule;
 * load b_K,i = sum_q w_q det(J_q) f(x_q) phi_i(xi_q) with f = 3 pi^2
-  prod sin(pi x_a) at the physical points, (k+2)^3 Gauss rule.
+  prod sin(pi x_a) at the physical points (or a given f), (k+2)^3 Gauss rule.
 
 Everything is evaluated by explicit per-point loops over the Q_k node
 values (no sum factorization), in float64.
@@ -136,13 +136,30 @@ class DeformedGeometry:
     def diagonal(self):
         return np.einsum("qia,eqab,qib->ei", self.Gr, self.G, self.Gr)
 
-    def load_vector(self):
-        """b_K,i = int_K f phi_i with f = 3 pi^2 prod sin(pi x), (k+2)^3 Gauss rule."""
+    def load_vector(self, f=None):
+        """b_K,i = int_K f phi_i, (k+2)^3 Gauss rule on the reference cell, det J
+        at each point.  f: callable on physical points (..., 3); default the
+        manufactured source 3 pi^2 prod sin(pi x_a) of u = prod sin(pi x_a)."""
         k = self.mesh.k
         xq, wq = gauss_legendre(k + 2)
         V, Gr = tensor_basis(k, xq)
         W = tensor_weights(wq)
         xp = np.einsum("qj,ejd->eqd", V, self.X)
         J = np.einsum("qja,ejd->eqda", Gr, self.X)
-        f = 3 * np.pi ** 2 * np.prod(np.sin(np.pi * xp), axis=-1)
-        return np.einsum("qi,eq->ei", V, f * np.linalg.det(J) * W[None, :])
+        if f is None:
+            fq = 3 * np.pi ** 2 * np.prod(np.sin(np.pi * xp), axis=-1)
+        else:
+            fq = f(xp)
+        return np.einsum("qi,eq->ei", V, fq * np.linalg.det(J) * W[None, :])
+
+    def l2_error(self, u_cell, u_exact):
+        """|| u_h - u ||_L2 over the mapped domain, (k+3)^3 Gauss rule: u_h from the
+        cell-wise nodal values, u_exact a callable on physical points."""
+        k = self.mesh.k
+        xq, wq = gauss_legendre(k + 3)
+        V, Gr = tensor_basis(k, xq)
+        W = tensor_weights(wq)
+        xp = np.einsum("qj,ejd->eqd", V, self.X)
+        det = np.linalg.det(np.einsum("qja,ejd->eqda", Gr, self.X))
+        uh = np.einsum("qj,ej->eq", V, np.asarray(u_cell).reshape(self.X.shape[0], -1))
+        return np.sqrt(np.sum(W[None, :] * det * (uh - u_exact(xp)) ** 2))

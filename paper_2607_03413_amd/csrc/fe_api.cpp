@@ -380,12 +380,22 @@ fe_status patch_fdm_inverse_level(const fe_problem* cp, int level, const void* r
   if (factors != 0 && p->desc.geometry != FE_GEOM_DEFORMED)
     return fail(FE_EINVAL, "per-patch factors need the deformed geometry");
   hipStream_t s = (hipStream_t)stream;
-  Level& L = level_of(p, level);
   const int li = level < 0 ? (int)p->levels.size() - 1 : level;
-  if (factors != 0 && !L.patch_eig_ready[factors]) FE_CHECK(setup_patch_factors(p, li, factors, s));
-  DeviceBuf& scr = L.fdm_scratch[dt == FE_F64 ? 0 : 1];
-  FE_CHECK(scr.alloc(patch_scratch_bytes(p, li, dt)));
-  return launch_patch_inverse(p, li, r, z, scr.p, dt, factors, s);
+  FE_CHECK(prepare_patch_inverse(p, li, dt, factors, s));   // no-op once prepared
+  return launch_patch_inverse(p, li, r, z, p->levels[li].fdm_scratch[dt == FE_F64 ? 0 : 1].p, dt, factors, s);
+}
+
+fe_status fe_patch_prepare(fe_problem* p, int level, fe_dtype dt, int factors, void* stream) {
+  if (!p) return fail(FE_EINVAL, "null problem");
+  FE_CHECK(check_dt(dt));
+  FE_CHECK(check_level(p, level));
+  if (factors < 0 || factors > 3) return fail(FE_EINVAL, "factors must be 0, 1, 2 or 3");
+  if (factors == 0 && p->desc.geometry != FE_GEOM_CARTESIAN)
+    return fail(FE_EINVAL, "exact separable factors need the Cartesian mesh");
+  if (factors != 0 && p->desc.geometry != FE_GEOM_DEFORMED)
+    return fail(FE_EINVAL, "per-patch factors need the deformed geometry");
+  const int li = level < 0 ? (int)p->levels.size() - 1 : level;
+  return prepare_patch_inverse(p, li, dt, factors, (hipStream_t)stream);
 }
 
 fe_status patch_fdm_inverse(const fe_problem* p, const void* r, void* z, fe_dtype dt, int factors, void* stream) {
@@ -573,6 +583,16 @@ static fe_status ensure_dinv(fe_problem* p, int li, hipStream_t s) {
 }
 
 namespace fe {
+// Set-up of the patch inverse on level li: the per-patch factors of a factor
+// mode (deformed mesh) and the scratch of the two-pass kernels in dtype dt
+// (allocated once, kept until the problem is destroyed).
+fe_status prepare_patch_inverse(fe_problem* p, int li, fe_dtype dt, int factors, hipStream_t s) {
+  Level& L = p->levels[li];
+  if (factors != 0 && !L.patch_eig_ready[factors]) FE_CHECK(setup_patch_factors(p, li, factors, s));
+  if (!fused_patch_supported(p, factors != 0))
+    FE_CHECK(L.fdm_scratch[dt == FE_F64 ? 0 : 1].alloc(patch_scratch_bytes(p, li, dt)));
+  return FE_OK;
+}
 fe_status ensure_dinv_level(fe_problem* p, int li, hipStream_t s) { return ::ensure_dinv(p, li, s); }
 fe_status ensure_coarse_inverse(fe_problem* p, hipStream_t s) {
   if (p->coarse_ready) return FE_OK;

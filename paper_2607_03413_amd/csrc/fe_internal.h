@@ -170,6 +170,10 @@ fe_status launch_patch_inverse(const fe_problem* p, int level, const void* r, vo
 fe_status launch_patch_cheb(const fe_problem* p, int level, const void* r, void* v, void* scratch, fe_dtype dt,
                             int factors, double a, double c, void* w, void* e, int e_zero, hipStream_t s);
 size_t patch_scratch_bytes(const fe_problem* p, int level, fe_dtype dt);
+// the one-pass (scratch-free) patch inverse serves this problem and factor kind
+bool fused_patch_supported(const fe_problem* p, bool per_patch);
+// per-patch factors of `factors` and the patch scratch in dtype dt on level li
+fe_status prepare_patch_inverse(fe_problem* p, int li, fe_dtype dt, int factors, hipStream_t s);
 fe_status launch_prolongate_add(const fe_problem* p, int fine_level, const void* ec, void* ef,
                                 fe_dtype dt, hipStream_t s);
 fe_status launch_restrict(const fe_problem* p, int fine_level, const void* bf, const void* vf, void* bc,

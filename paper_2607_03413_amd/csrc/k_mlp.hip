@@ -24,6 +24,9 @@ constexpr int kIn = 64, kHid = 64, kOut = 12;
 static_assert(kIn <= 256 && kHid <= 256, "k_layer_bwd_w splits the batch over 256 / nin thread groups");
 constexpr int kW1 = kHid * kIn, kW2 = kHid * kHid, kW3 = kOut * kHid;
 constexpr int kParams = kW1 + kHid + kW2 + kHid + kW3 + kOut;   // 9100
+// Rows whose loss partials (ceil(rows * kOut / 256), one per block) fit the
+// 1024 partial slots of the reduction scratch, below its result slot (2040).
+constexpr int kMaxLossRows = 1024 * 256 / kOut;   // 21845
 
 fe_status averaged_patch_weights(fe_problem* p, int level, DeviceBuf& weights, hipStream_t s);
 
@@ -323,7 +326,6 @@ __global__ void __launch_bounds__(256) k_layer_bwd_delta(const float* __restrict
   dprev[gid] = s * (1.0f - ai * ai);
 }
 
-// gW[o, i] = sum_b d[b, o] x[b, i]; gb[o] = sum_b d[b, o]  (one thread per weight, batch order fixed)
 // Weight and bias gradients of one layer: gW[o][i] = sum_b d[b][o] X[b][i],
 // gb[o] = sum_b d[b][o].  One block per output o; the batch is split over
 // Q = 256 / nin groups of nin threads (thread (q, i) sums rows b = q, q+Q, ...
@@ -755,13 +757,15 @@ fe_status fe_mlp_loss_grad(fe_problem* p, const float* X, const float* T, int n,
   FE_CHECK(check_ptr(T, "T"));
   FE_CHECK(check_ptr(grad, "grad"));
   if (n < 1 || !loss) return fail(FE_EINVAL, "bad arguments");
+  // the loss partials (one per 256 outputs) must stay below the result slot of
+  // the reduction scratch: checked before anything is launched
+  if (n > kMaxLossRows) return fail(FE_EINVAL, "batch too large for the loss reduction (n > 21845)");
   hipStream_t s = (hipStream_t)stream;
   MlpWork w;
   FE_CHECK(w.ensure(n));
   int nparts = 0;
   FE_CHECK(mlp_forward(p->mlp_params.as<float>(), X, n, w, s));
   FE_CHECK(mlp_backward(p->mlp_params.as<float>(), X, T, n, w, p->red_scratch.as<double>(), &nparts, s));
-  if (nparts > 1024) return fail(FE_EINVAL, "batch too large for the loss reduction");
   FE_CHECK(finish_reduction(p, nparts, p->red_scratch.as<double>() + 2040, s));
   FE_HIP_CHECK(hipMemcpyAsync(grad, w.g.p, kParams * 4, hipMemcpyDeviceToDevice, s));
   double tot = 0.0;
@@ -791,6 +795,7 @@ fe_status fe_mlp_train(fe_problem* p, const float* X, const float* T, int n, int
   FE_CHECK(check_ptr(X, "X"));
   FE_CHECK(check_ptr(T, "T"));
   if (n < 1 || epochs < 0 || batch < 1 || batch > 4096 || !(lr > 0)) return fail(FE_EINVAL, "bad arguments");
+  static_assert(4096 <= kMaxLossRows, "training batches must fit the loss reduction");
   hipStream_t s = (hipStream_t)stream;
   MlpWork w;
   FE_CHECK(w.ensure(batch));

@@ -40,6 +40,11 @@ struct Solver {
   fe_pcg_opts graph_opts{};
   const void* graph_r = nullptr;
   void* graph_z = nullptr;
+  // level work buffers (e, t of the inner dtype, per level) as they were at
+  // capture: the Jacobi sweeps alternate e and t by swapping these pointers, so
+  // a call outside the graph (fe_vcycle with an odd sweep count) can leave
+  // them swapped, and the graph would then write where pcg_solve no longer reads
+  std::vector<void*> graph_bufs;
   void drop_graph() {
     if (graph) (void)hipGraphExecDestroy(graph);
     graph = nullptr;
@@ -65,20 +70,17 @@ static fe_status read_scalar(fe_problem* p, int i, double* out, hipStream_t s) {
   return FE_OK;
 }
 
+// The patch inverse's scratch and factors are prepared at solver setup
+// (prepare_patch_inverse), so the V-cycle's launches allocate nothing.
 static fe_status patch_apply(fe_problem* p, int l, const void* r, void* z, fe_dtype dt, int factors, hipStream_t s) {
-  Level& L = p->levels[l];
-  DeviceBuf& scr = L.fdm_scratch[dt == FE_F64 ? 0 : 1];
-  FE_CHECK(scr.alloc(patch_scratch_bytes(p, l, dt)));
-  return launch_patch_inverse(p, l, r, z, scr.p, dt, factors, s);
+  return launch_patch_inverse(p, l, r, z, p->levels[l].fdm_scratch[dt == FE_F64 ? 0 : 1].p, dt, factors, s);
 }
 
 // v = P r, then w = a v + c w and e = w (e_zero) or e += w
 static fe_status patch_cheb(fe_problem* p, int l, const void* r, void* v, fe_dtype dt, int factors, double a, double c,
                             void* w, void* e, int e_zero, hipStream_t s) {
-  Level& L = p->levels[l];
-  DeviceBuf& scr = L.fdm_scratch[dt == FE_F64 ? 0 : 1];
-  FE_CHECK(scr.alloc(patch_scratch_bytes(p, l, dt)));
-  return launch_patch_cheb(p, l, r, v, scr.p, dt, factors, a, c, w, e, e_zero, s);
+  return launch_patch_cheb(p, l, r, v, p->levels[l].fdm_scratch[dt == FE_F64 ? 0 : 1].p, dt, factors, a, c, w, e,
+                           e_zero, s);
 }
 
 // lambda_max of P A on level l by CG-Lanczos from a fixed start vector; P is the
@@ -89,6 +91,7 @@ static fe_status estimate_lmax(fe_problem* p, int l, int smoother, int factors, 
   Level& L = p->levels[l];
   const int64_t n = L.len;
   if (smoother == FE_SMOOTH_JACOBI) FE_CHECK(ensure_dinv_level(p, l, s));
+  if (smoother == FE_SMOOTH_CHEB_FDM) FE_CHECK(prepare_patch_inverse(p, l, FE_F64, factors, s));
   auto precond = [&](const void* rr, void* zz) -> fe_status {
     if (smoother == FE_SMOOTH_JACOBI)
       return launch_jacobi_avg(p, l, rr, rr, rr, L.dinv64.p, zz, 1.0, 1, FE_F64, s);
@@ -189,14 +192,17 @@ fe_status solver_setup(fe_problem* p, const fe_pcg_opts* o, hipStream_t s) {
       }
     }
     if (l > 0 && o->smoother == FE_SMOOTH_CHEB_FDM) {
-      if (o->factors != 0 && !L.patch_eig_ready[o->factors]) FE_CHECK(setup_patch_factors(p, l, o->factors, s));
+      FE_CHECK(prepare_patch_inverse(p, l, (fe_dtype)o->inner, o->factors, s));
       const int key = o->factors * 1000 + 15;
+      // L.lmax is the top of the Chebyshev interval: a caller's value as given,
+      // a Lanczos estimate (which approaches lambda_max from below) times 1.2
       if (o->cheb_lmax > 0.0) {
         L.lmax = o->cheb_lmax;
+        L.lmax_key = -1;
       } else if (L.lmax_key != key) {
         double lm;
         FE_CHECK(estimate_lmax(p, l, FE_SMOOTH_CHEB_FDM, o->factors, 15, &lm, s));
-        L.lmax = lm;
+        L.lmax = 1.2 * lm;
         L.lmax_key = key;
       }
     }
@@ -238,7 +244,7 @@ static fe_status cheb_smooth(fe_problem* p, int l, int sweeps, bool u_zero, fe_d
   Level& L = p->levels[l];
   const int di = dt == FE_F64 ? 0 : 1;
   const fe_pcg_opts& o = p->solver->opts;
-  const double lmax = 1.2 * L.lmax, lmin = lmax / o.cheb_ratio;
+  const double lmax = L.lmax, lmin = lmax / o.cheb_ratio;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   void *e = L.e[di].p, *b = L.b[di].p, *t = L.t[di].p, *w = L.w[di].p, *v = L.v[di].p;
   for (int sw = 0; sw < sweeps; ++sw) {
@@ -315,6 +321,16 @@ static bool same_vcycle(const fe_pcg_opts& a, const fe_pcg_opts& b) {
   return same_setup(a, b) && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post;
 }
 
+static std::vector<void*> level_bufs(fe_problem* p) {
+  const int di = p->solver->opts.inner == FE_F64 ? 0 : 1;
+  std::vector<void*> v;
+  for (const Level& L : p->levels) {
+    v.push_back(L.e[di].p);
+    v.push_back(L.t[di].p);
+  }
+  return v;
+}
+
 // z = M r, replayed as a HIP graph once the same application has run eagerly
 // with the current setup (the eager run performs any first-use allocation,
 // which capture would reject).  A V-cycle is a fixed sequence of launches on
@@ -330,7 +346,8 @@ static fe_status apply_precond(fe_problem* p, const void* r, void* z, hipStream_
     S.drop_graph();
     return precondition(p, r, z, s);
   }
-  if (S.graph && S.graph_gen == S.gen && same_vcycle(S.graph_opts, o) && S.graph_r == r && S.graph_z == z) {
+  if (S.graph && S.graph_gen == S.gen && same_vcycle(S.graph_opts, o) && S.graph_r == r && S.graph_z == z &&
+      S.graph_bufs == level_bufs(p)) {
     FE_HIP_CHECK(hipGraphLaunch(S.graph, s));
     return FE_OK;
   }
@@ -341,6 +358,7 @@ static fe_status apply_precond(fe_problem* p, const void* r, void* z, hipStream_
     return precondition(p, r, z, s);
   }
   hipGraph_t g = nullptr;
+  const std::vector<void*> bufs = level_bufs(p);
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return precondition(p, r, z, s);
   const fe_status st = precondition(p, r, z, s);
   const hipError_t ec = hipStreamEndCapture(s, &g);
@@ -357,6 +375,7 @@ static fe_status apply_precond(fe_problem* p, const void* r, void* z, hipStream_
   S.graph_opts = o;
   S.graph_r = r;
   S.graph_z = z;
+  S.graph_bufs = bufs;
   FE_HIP_CHECK(hipGraphLaunch(ex, s));
   return FE_OK;
 }

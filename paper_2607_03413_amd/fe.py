@@ -72,6 +72,7 @@ _SIGS = {
     "fe_apply_level": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
     "patch_fdm_inverse": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "patch_fdm_inverse_level": (_i, [_vp, _i, _vp, _vp, _i, _i, _vp]),
+    "fe_patch_prepare": (_i, [_vp, _i, _i, _i, _vp]),
     "fe_prolongate_add": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
     "fe_restrict_residual": (_i, [_vp, _i, _vp, _vp, _vp, _i, _vp]),
     "fe_jacobi_sweep": (_i, [_vp, _i, _vp, _vp, _vp, _d, _i, _i, _vp]),
@@ -211,6 +212,9 @@ class Problem:
     def patch_inverse(self, r, z, factors=0, level=-1):
         _check(_lib.patch_fdm_inverse_level(self.h, level, _ptr(r, name="r"), _ptr(z, name="z"), _dt(r), factors,
                                             _stream()))
+
+    def patch_prepare(self, dtype=torch.float64, factors=0, level=-1):
+        _check(_lib.fe_patch_prepare(self.h, level, F64 if dtype == torch.float64 else F32, factors, _stream()))
 
     def prolongate_add(self, fine_level, ec, ef):
         _check(_lib.fe_prolongate_add(self.h, fine_level, _ptr(ec, name="e_coarse"), _ptr(ef, name="e_fine"),

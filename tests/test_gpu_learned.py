@@ -126,10 +126,30 @@ def test_training_reduces_loss_and_learned_factors_help_pcg(gpu_lib):
         assert rep["converged"]
         its[factors] = rep["iters"]
     # learned factors are no worse than the averaged fallback, and within one
-    # iteration of the per-patch best fits they were trained on
-    print("PCG iterations: averaged %d, learned %d, best fit %d" % (its[1], its[2], its[3]))
-    assert its[2] <= its[1] + 1, its
+    # iteration of the per-patch best fits they were trained on (the gap to
+    # that ceiling is printed; at this deformation the separable family is
+    # saturated and all three counts are equal)
+    print("PCG iterations: averaged %d, learned %d, best fit %d (learned - best fit = %d)"
+          % (its[1], its[2], its[3], its[2] - its[3]))
+    assert its[2] <= its[1], its
     assert its[2] <= its[3] + 1, its
+
+
+def test_loss_grad_rejects_batches_beyond_the_reduction(gpu_lib):
+    """The loss partials of n rows take ceil(12 n / 256) slots of a 1024-slot
+    reduction: n = 21846 is refused before anything is launched, n = 21845 works."""
+    fe = gpu_lib
+    P = problem(fe, 2, 3)
+    P.mlp_set_params(torch.as_tensor(init_params(20), dtype=torch.float32, device="cuda"))
+    X = torch.zeros(21846, 64, dtype=torch.float32, device="cuda")
+    T = torch.zeros(21846, 12, dtype=torch.float32, device="cuda")
+    with pytest.raises(fe.FeError) as ei:
+        P.mlp_loss_grad(X, T)
+    assert ei.value.status == -1 and "too large" in str(ei.value)
+    loss, g = P.mlp_loss_grad(X[:21845], T[:21845])
+    assert np.isfinite(loss) and torch.isfinite(g).all()
+    with pytest.raises(fe.FeError):
+        P.mlp_train(X, T, epochs=1, batch=4097)
 
 
 def test_retrained_model_refreshes_learned_factors(gpu_lib):

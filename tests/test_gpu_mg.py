@@ -108,9 +108,9 @@ def test_chebyshev_fdm_vcycle_equals_classical(gpu_lib, k, n, inner):
     h = Hierarchy(3, k, n)
     P = fe.Problem(3, k, n, bc=1)
     lev = h.levels[-1]
-    lhat = 1.7   # lambda_max estimate handed to both sides; interval [1.2 lhat / 20, 1.2 lhat]
+    lhat = 2.04   # top of the Chebyshev interval handed to both sides; interval [lhat / 20, lhat]
     b = uniform(lev.mesh.n_cellwise, seed=206)
-    sm = make_chebyshev_smoother([1.2 * lhat] * len(h.levels), degree=3, ratio=20.0, nu_pre=1, nu_post=1)
+    sm = make_chebyshev_smoother([lhat] * len(h.levels), degree=3, ratio=20.0, nu_pre=1, nu_post=1)
     expect = to_cell(lev, vcycle(h, to_int(lev, b), sm))
     dtype = torch.float64 if inner == 0 else torch.float32
     opts = fe.default_opts(inner=inner, smoother=fe.SMOOTH_CHEB_FDM, cheb_degree=3, cheb_ratio=20.0,

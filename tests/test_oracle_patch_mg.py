@@ -141,7 +141,7 @@ def _contraction(h, M, A, cycles=12, seed=21):
 
 @pytest.mark.slow
 def test_jacobi_vcycle_contraction_against_paper():
-    """Paper, Sec. 7.1: contraction 0.36 (p=2) to 0.49 (p=4) per V-cycle, omega = 0.7.
+    """Paper, Sec. 6.1: contraction 0.36 (p=2) to 0.49 (p=4) per V-cycle, omega = 0.7.
 
     The paper's 'two smoothing steps' is read as nu1 = nu2 = 2; the contraction
     of the classical V-cycle must then be no worse than the paper's figures and
