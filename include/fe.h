@@ -143,6 +143,25 @@ fe_status patch_fdm_inverse_level(const fe_problem* prob, int level, const void*
  * runs this set-up first.  pcg_solve prepares every level it smooths on. */
 fe_status fe_patch_prepare(fe_problem* prob, int level, fe_dtype dt, int factors, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as patch_fdm_inverse_level, bit for bit, with the two-pass
+ * kernels' patch-solution scratch taken from a fixed device array of
+ * fe_noalloc_scratch_bytes() = 64 MiB that the library holds on every GPU it
+ * runs on until the process ends.  No hipMalloc, hipFree or other allocating
+ * call is made.  Errors: FE_EINVAL when the scratch this (level, dt) needs
+ * (patch_fdm_inverse's two-pass kernels: (n_l - 1)^d patches x 8 k^3 values in
+ * 3D, x (2k-1)^2 in 2D) exceeds 64 MiB, or when factors >= 1 and the per-patch
+ * factors of that level were not set up (call fe_patch_prepare first, which
+ * does allocate); the scratch-free one-pass kernels (3D Cartesian, k = 2, 3)
+ * have no size limit.  All calls on one GPU share the one array: calls that
+ * overlap in time on one GPU (different streams or threads) race and give
+ * wrong results.  The array keeps the last call's contents; every entry a
+ * call reads is written by that call first. */
+size_t fe_noalloc_scratch_bytes(void);
+fe_status patch_fdm_inverse_noalloc(const fe_problem* prob, int level, const void* r_cell, void* z_cell,
+                                    fe_dtype dt, int factors, void* stream);
+
 /* Sec. 3.1 Algorithm 2: e_fine += (P_b1 x P_b2 x P_b3) e_coarse on every
  * child, level `fine_level` >= 1.  Continuous in, continuous out (lemma on
  * commutativity of prolongation). */

@@ -73,6 +73,8 @@ _SIGS = {
     "patch_fdm_inverse": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "patch_fdm_inverse_level": (_i, [_vp, _i, _vp, _vp, _i, _i, _vp]),
     "fe_patch_prepare": (_i, [_vp, _i, _i, _i, _vp]),
+    "fe_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "patch_fdm_inverse_noalloc": (_i, [_vp, _i, _vp, _vp, _i, _i, _vp]),
     "fe_prolongate_add": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
     "fe_restrict_residual": (_i, [_vp, _i, _vp, _vp, _vp, _i, _vp]),
     "fe_jacobi_sweep": (_i, [_vp, _i, _vp, _vp, _vp, _d, _i, _i, _vp]),
