@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-deformed", action="store_true")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's cube solves (p = 2..5, 128^3)")
+    ap.add_argument("--only-paper", action="store_true", help="run the paper's cube solves only")
     ap.add_argument("--only-step", action="store_true", help="time the headline step only (for profilers)")
     ap.add_argument("--with-copy", action="store_true", help="with --only-step: add a plain copy kernel of known size")
     ap.add_argument("--only-pcg", action="store_true", help="run the Q7 32^3 MG-PCG solves only (for profilers)")
@@ -164,6 +166,20 @@ def bench_config(fe, degree, n, dtype, steps, warmup, nsets):
     return res
 
 
+def timed_solve(P, b, opts, name):
+    """First solve (its setup: levels, diagonals, Lanczos estimates, per-patch factors, graph
+    capture), then a second solve from zero with the setup cached; both reported."""
+    x = P.cellvec()
+    first = P.pcg_solve(b, x, opts, raise_on_error=False)
+    x.zero_()
+    rep = P.pcg_solve(b, x, opts, raise_on_error=False)
+    log("pcg %s: %.4f s, %d iters, relres %.2e (first solve: setup %.3f s, solve %.4f s)"
+        % (name, rep["t_solve"], rep["iters"], rep["relres"], first["t_setup"], first["t_solve"]))
+    return {"seconds": rep["t_solve"], "iters": rep["iters"], "relres": rep["relres"],
+            "first_setup_s": first["t_setup"], "first_solve_s": first["t_solve"],
+            "converged": rep["converged"], "status": rep["status"]}
+
+
 def bench_pcg(fe):
     """Q7 32^3, manufactured RHS, tol 1e-10: FP32 Chebyshev(3) patch-FDM MG inside FP64 CG vs FP64 Jacobi MG."""
     import torch
@@ -174,15 +190,11 @@ def bench_pcg(fe):
     for name, opts in (
             ("fp32_chebfdm_flexible", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
                                                       nu_pre=1, nu_post=1, tol=1e-10)),
+            ("fp64_chebfdm", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F64, nu_pre=1, nu_post=1,
+                                             tol=1e-10)),
             ("fp64_jacobi_plain", fe.default_opts(smoother=fe.SMOOTH_JACOBI, inner=fe.F64, omega=0.7,
                                                   nu_pre=2, nu_post=2, tol=1e-10, maxit=400))):
-        x = P.cellvec()
-        P.pcg_solve(b, x, opts, raise_on_error=False)     # includes setup
-        x.zero_()
-        rep = P.pcg_solve(b, x, opts, raise_on_error=False)  # timed solve with setup cached
-        out[name] = {"seconds": rep["t_solve"], "iters": rep["iters"], "relres": rep["relres"],
-                     "setup_s": rep["t_setup"], "converged": rep["converged"], "status": rep["status"]}
-        log("pcg %s: %.4f s, %d iters, relres %.2e" % (name, rep["t_solve"], rep["iters"], rep["relres"]))
+        out[name] = timed_solve(P, b, opts, name)
     P.close()
     torch.cuda.empty_cache()
     return out
@@ -221,24 +233,26 @@ def bench_deformed(fe, k, n, n_train, train_meshes, epochs, with_solve=True, max
     out["targets_s"] = time.perf_counter() - t0
     P = fe.Problem(3, k, n, geometry=fe.GEOM_DEFORMED, bc=1, deform_amp=0.1, coef=coefficient_modes(2))
     out["unique_dofs"] = P.n_dofs
-    # general apply rate
+    # general apply rate: one (x, y) pair, and 4 rotated pairs (working set beyond the
+    # 256 MB last-level cache: the HBM rate)
     for dtype, name in ((torch.float64, "fp64"), (torch.float32, "fp32")):
-        x = torch.as_tensor(uniform(P.len, seed=7), dtype=dtype, device="cuda")
-        y = P.cellvec(dtype)
-        for _ in range(3):
-            P.apply(x, y)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            P.apply(x, y)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 10
         s = 8 if dtype == torch.float64 else 4
-        out["apply_" + name] = {"ms": ms, "gdofs": P.n_dofs / ms / 1e6,
-                                "gbs_algorithmic": (2 * s + 6 * s) * P.len / ms / 1e6}
-        del x, y
+        for nsets, tag in ((1, ""), (4, "_rotated4")):
+            xs = [torch.as_tensor(uniform(P.len, seed=7 + i), dtype=dtype, device="cuda") for i in range(nsets)]
+            ys = [P.cellvec(dtype) for _ in range(nsets)]
+            for i in range(3):
+                P.apply(xs[i % nsets], ys[i % nsets])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(12):
+                P.apply(xs[i % nsets], ys[i % nsets])
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 12
+            out["apply_" + name + tag] = {"ms": ms, "gdofs": P.n_dofs / ms / 1e6,
+                                          "gbs_algorithmic": (2 * s + 6 * s) * P.len / ms / 1e6}
+            del xs, ys
     # model
     glorot = []
     for i, (no, ni) in enumerate([(64, 64), (64, 64), (12, 64)]):
@@ -261,20 +275,86 @@ def bench_deformed(fe, k, n, n_train, train_meshes, epochs, with_solve=True, max
                  ("fp32_chebfdm_learned", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
                                                           factors=2, nu_pre=1, nu_post=1, tol=1e-10)),
                  ("fp32_chebfdm_bestfit", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1,
-                                                          factors=3, nu_pre=1, nu_post=1, tol=1e-10)))
+                                                          factors=3, nu_pre=1, nu_post=1, tol=1e-10)),
+                 ("fp64_chebfdm_averaged", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F64,
+                                                           factors=1, nu_pre=1, nu_post=1, tol=1e-10)),
+                 ("fp64_chebfdm_learned", fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F64,
+                                                          factors=2, nu_pre=1, nu_post=1, tol=1e-10)))
         for name, opts in cases:
-            x = P.cellvec()
-            P.pcg_solve(b, x, opts, raise_on_error=False)
-            x.zero_()
-            rep = P.pcg_solve(b, x, opts, raise_on_error=False)
-            out[name] = {"seconds": rep["t_solve"], "iters": rep["iters"], "relres": rep["relres"],
-                         "status": rep["status"]}
-            log("deformed Q%d %d^3 %s: %.4f s, %d iters, relres %.2e" % (k, n, name, rep["t_solve"],
-                                                                       rep["iters"], rep["relres"]))
-            del x
+            out[name] = timed_solve(P, b, opts, "deformed Q%d %d^3 %s" % (k, n, name))
     P.close()
     torch.cuda.empty_cache()
     return out
+
+
+PAPER_CUBE = {   # Table mg_solve_time (Sec. 6.2), cube rows, A100 80 GB, fp64: context only
+    2: {"cg_iters": 8, "mg_mdofs": 522.1, "solve_mdofs": 44.7},
+    3: {"cg_iters": 9, "mg_mdofs": 1147.0, "solve_mdofs": 99.5},
+    4: {"cg_iters": 10, "mg_mdofs": 662.4, "solve_mdofs": 56.7},
+    5: {"cg_iters": 11, "mg_mdofs": 996.5, "solve_mdofs": 77.0},
+}
+
+
+def bench_paper_cube(fe, n=128, degrees=(2, 3, 4, 5)):
+    """The paper's cube solve (Sec. 6.2): masked Jacobi V-cycle (omega 0.7, one pre- and one
+    post-sweep), FP64, CG until <r, M r> has fallen by 1e-14, on 128^3 cells.  MG throughput =
+    DoFs / V-cycle time (events around 10 preconditioner applications), solve throughput =
+    DoFs / solve time; DoFs both as the paper estimates them (cells p^3) and exact."""
+    import torch
+    out = {}
+    for p in degrees:
+        P = fe.Problem(3, p, n, bc=1)
+        b = P.cellvec()
+        P.rhs_manufactured(b)
+        opts = fe.default_opts(smoother=fe.SMOOTH_JACOBI, inner=fe.F64, omega=0.7, nu_pre=1, nu_post=1,
+                               stop=1, tol=1e-14, maxit=100)
+        rec = timed_solve(P, b, opts, "paper cube p=%d %d^3" % (p, n))
+        e = P.cellvec()
+        for _ in range(2):
+            P.vcycle(b, e, opts)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            P.vcycle(b, e, opts)
+        e1.record()
+        torch.cuda.synchronize()
+        vc_s = e0.elapsed_time(e1) / 10 * 1e-3
+        est = n ** 3 * p ** 3
+        rec.update({"vcycle_s": vc_s, "dofs_exact": P.n_dofs, "dofs_paper_estimate": est,
+                    "mg_mdofs": est / vc_s / 1e6, "solve_mdofs": est / rec["seconds"] / 1e6,
+                    "mg_mdofs_exact": P.n_dofs / vc_s / 1e6, "solve_mdofs_exact": P.n_dofs / rec["seconds"] / 1e6,
+                    "paper_a100": PAPER_CUBE[p]})
+        log("paper cube p=%d: %d iters, V-cycle %.2f ms (%.0f MDoF/s), solve %.4f s (%.0f MDoF/s)"
+            % (p, rec["iters"], vc_s * 1e3, rec["mg_mdofs"], rec["seconds"], rec["solve_mdofs"]))
+        out["p%d" % p] = rec
+        del b, e
+        P.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def copy_bandwidth():
+    """A plain device copy (torch's elementwise copy kernel) over 4 rotated pairs of
+    1 GiB buffers: the achievable HBM rate of a streaming kernel in this run, in GB/s
+    (bytes read + written)."""
+    import torch
+    n = (1 << 30) // 8
+    srcs = [torch.ones(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    dsts = [torch.empty_like(s) for s in srcs]
+    for i in range(4):
+        dsts[i].copy_(srcs[i])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(20):
+        dsts[i % 4].copy_(srcs[i % 4])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    del srcs, dsts
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline():
@@ -286,9 +366,11 @@ def cpu_baseline():
     from synthetic_inputs import uniform
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])   # BLAS pool the oracle uses
     except Exception:
         cores = 1
+    nproc = os.cpu_count()
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else nproc
     k, n = 3, 16
     m = StructuredMesh(3, k, n)
     E = element_matrix_cartesian(3, k, m.h)
@@ -305,6 +387,7 @@ def cpu_baseline():
             break
     dt = (time.perf_counter() - t0) / reps
     return {"value": m.n_global / dt / 1e9, "unit": "GDoF/s", "cores": cores, "kind": "oracle",
+            "nproc": nproc, "affinity_cpus": affinity,
             "sample": "Q3 16^3 (%d DoFs) apply + patch inverse, FP64, %d repetitions in %.1f s" %
                       (m.n_global, reps, dt * reps)}
 
@@ -326,6 +409,9 @@ def main():
         return
     if args.only_deformed:
         print(json.dumps(bench_deformed_q7(fe)))
+        return
+    if args.only_paper:
+        print(json.dumps(bench_paper_cube(fe)))
         return
     if args.only_step and args.step_config != "q3":
         deg, n = (7, 32) if args.step_config.startswith("q7") else (3, 64)
@@ -353,6 +439,12 @@ def main():
     q7_64 = bench_config(fe, 7, 32, torch.float64, max(10, args.steps // 2), args.warmup, nsets=4)
     q7_32 = bench_config(fe, 7, 32, torch.float32, max(10, args.steps // 2), args.warmup, nsets=4)
     pcg = None if args.no_pcg else bench_pcg(fe)
+    paper = None
+    if not args.no_paper:
+        log("paper's cube solves, p = 2..5 on 128^3 cells")
+        paper = bench_paper_cube(fe)
+    copy_gbs = copy_bandwidth()
+    log("plain copy: %.0f GB/s" % copy_gbs)
     deformed = {}
     if not args.no_deformed:
         log("deformed Q3 48^3 (apply, learned vs averaged factors)")
@@ -369,7 +461,8 @@ def main():
     achieved = bytes_dom / (k_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
-            "avg_launch_ms": round(k_ms, 5), "algorithmic_bytes": bytes_dom}
+            "avg_launch_ms": round(k_ms, 5), "algorithmic_bytes": bytes_dom,
+            "copy_gbs_measured": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     line = {
         "metric": METRIC, "value": round(main64["gdofs"], 4), "unit": "GDoF/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main64["ms_per_step"], 5),
@@ -385,6 +478,7 @@ def main():
                        "fp32": {"value": round(q7_32["gdofs"], 4), "kernel_ms": q7_32["kernel_ms"]},
                        "unique_dofs": q7_64["n_dofs"]},
         "pcg_q7_32cubed": pcg,
+        "paper_cube_128cubed": paper,
         "deformed": deformed,
     }
     print(json.dumps(line))

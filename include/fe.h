@@ -213,6 +213,11 @@ typedef struct {
   int factors;             /* patch factors for smoother = 1 (see patch_fdm_inverse) */
   int flexible;            /* 1: Polak-Ribiere beta (recommended with inner = FE_F32) */
   int precond;             /* 1: V-cycle preconditioner, 0: none (plain CG) */
+  int stop;                /* 0: stop when ||G^T r||_2 <= tol ||G^T b||_2;
+                              1: stop when the energy pairing of the residual with its
+                                 preconditioned form, gamma = <r, M r> (Sec. 3.4 eq. energy_measure,
+                                 the square of a preconditioner-induced norm), has fallen to
+                                 tol * gamma_0 (Sec. 6 uses a 1e-14 reduction) */
 } fe_pcg_opts;
 
 typedef struct {
@@ -237,6 +242,17 @@ void fe_pcg_default_opts(fe_pcg_opts* opts);
  * maxit was reached. */
 fe_status pcg_solve(fe_problem* prob, const void* b_cell, void* x_cell, const fe_pcg_opts* opts,
                     fe_pcg_report* report, void* stream);
+
+/* Sec. 6.1: the V-cycle as a stationary iteration, x <- x + MG(b - A x),
+ * `cycles` times (Algorithm 1 with opts' smoother, sweeps and precision),
+ * recording after each cycle c the energy measure eta[c] = <b - A x, x> (Sec.
+ * 3.4 eq. energy_measure: a dual paired with a primal vector, no assembly)
+ * and res[c] = ||G^T (b - A x)||_2.  b: dual FP64 (boundary copies ignored);
+ * x: primal FP64, initial guess in (boundary copies set to zero), last
+ * iterate out.  eta, res: HOST arrays of `cycles` doubles, either may be NULL.
+ * Synchronous. */
+fe_status fe_mg_iterate(fe_problem* prob, const void* b_cell, void* x_cell, const fe_pcg_opts* opts, int cycles,
+                        double* eta, double* res, void* stream);
 
 /* One application of the V-cycle preconditioner e = MG(b) (Algorithm 1 with
  * a zero initial guess) on the finest level, in opts->inner precision.

@@ -47,7 +47,7 @@ class PcgOpts(ctypes.Structure):
                 ("nu_post", ctypes.c_int), ("smoother", ctypes.c_int), ("cheb_degree", ctypes.c_int),
                 ("cheb_ratio", ctypes.c_double), ("cheb_lmax", ctypes.c_double), ("omega", ctypes.c_double),
                 ("inner", ctypes.c_int), ("factors", ctypes.c_int), ("flexible", ctypes.c_int),
-                ("precond", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("stop", ctypes.c_int)]
 
 
 class PcgReport(ctypes.Structure):
@@ -84,6 +84,7 @@ _SIGS = {
     "fe_pcg_default_opts": (None, [ctypes.POINTER(PcgOpts)]),
     "pcg_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _vp]),
     "fe_vcycle": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), _i, _vp]),
+    "fe_mg_iterate": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), _i, _vp, _vp, _vp]),
     "fe_estimate_lmax": (_i, [_vp, _i, _i, _i, _i, ctypes.POINTER(_d), _vp]),
     "fe_mlp_num_params": (_i, []),
     "fe_num_patches": (_i64, [_vp, _i]),
@@ -247,6 +248,15 @@ class Problem:
     def vcycle(self, b, e, opts):
         _check(_lib.fe_vcycle(self.h, _ptr(b, self.len, "b"), _ptr(e, self.len, "e"), ctypes.byref(opts), _dt(b),
                               _stream()))
+
+    def mg_iterate(self, b, x, opts, cycles):
+        """x <- x + MG(b - A x), `cycles` times; returns (eta, res) per cycle (numpy)."""
+        eta = np.zeros(max(cycles, 1))
+        res = np.zeros(max(cycles, 1))
+        _check(_lib.fe_mg_iterate(self.h, _ptr(b, self.len, "b"), _ptr(x, self.len, "x"), ctypes.byref(opts),
+                                  cycles, eta.ctypes.data_as(ctypes.c_void_p), res.ctypes.data_as(ctypes.c_void_p),
+                                  _stream()))
+        return eta[:cycles], res[:cycles]
 
     def estimate_lmax(self, level=-1, factors=0, steps=15, smoother=SMOOTH_CHEB_FDM):
         out = ctypes.c_double()
