@@ -332,6 +332,85 @@ fe_status fe_prof_query(const char* name, int* count, double* total_ms);
  * (whose sweeps alternate buffers between applications).  Process-wide. */
 void fe_set_graphs(int enable);
 
+/* ---- Locally refined meshes: local multigrid (Sec. 3.2, Algorithms 4-5) ----
+ * The unit cube refined as an octree: levels 0..g uniform (level l has 2^l
+ * cells per direction), then up to `adaptive_refinements` levels on which only
+ * the cells near a feature are refined, 2:1 balanced across faces, edges and
+ * vertices.  The level mesh T_l holds ALL level-l cells (active leaves and
+ * cells refined further); level 0 is the single cell of the cube.  Storage:
+ * level l >= 1 lists its cells in bricks of 8, the children (c = bx + 2 by +
+ * 4 bz) of the refined level-(l-1) cells taken in their order; each cell keeps
+ * (k+1)^3 values (local index x fastest).  A vector of the active mesh is kept
+ * in LEVEL LAYOUT: the level blocks concatenated (offsets from
+ * fe_adaptive_level_offset), zeros on refined cells.  Primal vectors are
+ * continuous on the active mesh (hanging copies interpolate the coarse side);
+ * dual vectors are unassembled.  Homogeneous Dirichlet conditions on the cube.
+ * FP64 only; all vector pointers are device pointers owned by the caller.
+ * No hanging-node constraint is stored or applied: the smoother masks the
+ * refinement edge E_l (found at setup by one DSS of a face marker, Sec. 5) on
+ * both sides of the structured DSS cascade (Sec. 4.3), and the transfers act
+ * on unassembled residuals (lemma on the residual transfer). */
+typedef struct fe_adaptive fe_adaptive;
+typedef enum { FE_FEATURE_SPHERE = 0, FE_FEATURE_POINT = 1 } fe_feature;
+typedef struct {
+  int degree;                /* k, 1..5 */
+  int global_refinements;    /* g: uniform levels 0..g */
+  int adaptive_refinements;  /* levels beyond g refined toward the feature (g + this <= 12) */
+  int feature;               /* fe_feature */
+  double center[3];          /* sphere centre / the point */
+  double radius;             /* sphere radius */
+  double band;               /* refine a level-l cell whose centre is within band * 2^-l of the feature
+                                (dyadic centre, radius and band make the test exact) */
+} fe_adaptive_desc;
+
+/* Builds the tree, the per-level brick tables, the masked valence-baked
+ * inverse diagonals (Algorithm 9) and the coarse solve.  Synchronous. */
+fe_status fe_adaptive_create(const fe_adaptive_desc* desc, void* stream, fe_adaptive** out);
+void fe_adaptive_destroy(fe_adaptive* a);
+int fe_adaptive_num_levels(const fe_adaptive* a);                 /* L + 1 */
+int64_t fe_adaptive_level_cells(const fe_adaptive* a, int level);  /* cells of T_l */
+int64_t fe_adaptive_level_offset(const fe_adaptive* a, int level); /* level = L+1: total length */
+int64_t fe_adaptive_active_cells(const fe_adaptive* a);            /* leaves */
+/* Host copies: coords (n_cells x 3 int32, level-l integer cell coordinates),
+ * refined (n_cells bytes); either may be NULL. */
+fe_status fe_adaptive_level_info(const fe_adaptive* a, int level, int32_t* coords, uint8_t* refined);
+/* Host copies for level >= 1: nbr (n_bricks x 6: brick of the -x, +x, -y, +y,
+ * -z, +z neighbour, -1 if absent), parent (n_bricks: parent cell on level-1). */
+fe_status fe_adaptive_brick_neighbors(const fe_adaptive* a, int level, int32_t* nbr, int32_t* parent);
+/* Sec. 5, detection of the refinement edge: mask (device, level length) >= 1 on
+ * the copies of E_l, 0 elsewhere -- the summed face marker. */
+fe_status fe_adaptive_edge_mask(fe_adaptive* a, int level, double* mask, void* stream);
+/* Algorithm 7 on level l (in place; averaging = 1: S_bar): the structured
+ * cascade of brick and neighbour-brick pairs, pairs without a partner skipped. */
+fe_status fe_adaptive_dss(fe_adaptive* a, int level, double* v, int averaging, void* stream);
+/* Copy of the masked, valence-baked inverse diagonal of level >= 1 (Algorithm 9). */
+fe_status fe_adaptive_dinv(const fe_adaptive* a, int level, double* dinv, void* stream);
+/* y = A_act x over the level layout (cell by cell; refined cells give 0). */
+fe_status fe_adaptive_apply(fe_adaptive* a, const double* x, double* y, void* stream);
+/* Algorithm 2 / Algorithm 3 between level fine_level - 1 and fine_level
+ * (level blocks, not the level layout): e_fine += P e_coarse on the children
+ * of every refined coarse cell; b_coarse += R (b_fine - v_fine) on every
+ * refined coarse cell. */
+fe_status fe_adaptive_prolongate_add(fe_adaptive* a, int fine_level, const double* e_coarse, double* e_fine,
+                                     void* stream);
+fe_status fe_adaptive_restrict_add(fe_adaptive* a, int fine_level, const double* b_fine, const double* v_fine,
+                                   double* b_coarse, void* stream);
+/* Manufactured load vector on the active cells (f = 3 pi^2 prod sin(pi x_a)). */
+fe_status fe_adaptive_rhs_manufactured(fe_adaptive* a, double* b, void* stream);
+/* Algorithm 4 from a zero iterate: z = MG_local(r), level distribution of the
+ * unassembled residual r, the local V-cycle of Algorithm 5 with opts' Jacobi
+ * omega and sweeps (smoother = FE_SMOOTH_JACOBI, inner = FE_F64), reassembly
+ * of the active components.  r, z: level layout. */
+fe_status fe_adaptive_precondition(fe_adaptive* a, const double* r, double* z, const fe_pcg_opts* opts,
+                                   void* stream);
+/* CG in primal-dual form on the active mesh preconditioned by Algorithm 4;
+ * opts->stop must be 1 (gamma = <r, z> reduced to tol * gamma_0; relres in the
+ * report is sqrt(gamma / gamma_0)).  b: dual, x: primal initial guess in,
+ * solution out (level layout; refined and Dirichlet copies are zeroed).
+ * Synchronous. */
+fe_status fe_adaptive_pcg(fe_adaptive* a, const double* b, double* x, const fe_pcg_opts* opts,
+                          fe_pcg_report* report, void* stream);
+
 /* Thread-local description of the last non-OK status. */
 const char* fe_last_error(void);
 

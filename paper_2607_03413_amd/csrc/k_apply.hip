@@ -264,4 +264,41 @@ fe_status launch_diag_cartesian(const fe_problem* p, int level, void* d, fe_dtyp
   }
 }
 
+// The cube operator on a plain list of n_cells cells of side h (3D, FP64, no
+// boundary treatment: inputs are zero on Dirichlet copies by construction):
+// the cells of one level of a locally refined hierarchy.
+template <int K>
+static fe_status apply_cells_typed(const fe_problem* p, int64_t n_cells, double h, const double* x, double* y,
+                                   double alpha, double beta, const double* b, hipStream_t s) {
+  if (n_cells == 0) return FE_OK;
+  const double* coef = p->coef64.as<double>();
+  constexpr int CPB = 256 / (K * K);
+  const int64_t nb = (n_cells + CPB - 1) / CPB;
+  ProfScope ps("apply", s);
+  hipLaunchKernelGGL((k_apply_cart3<double, K>), dim3((unsigned)nb), dim3(CPB * K * K), 0, s, x, y,
+                     coef + p->co.off_B, coef + p->co.off_D, h, 1, n_cells, 0, alpha, beta, b);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status launch_apply_cells(const fe_problem* p, int64_t n_cells, double h, const double* x, double* y, double alpha,
+                             double beta, const double* b, hipStream_t s) {
+  if (p->dim != 3) return fail(FE_EINVAL, "cell-list apply is 3D");
+  FE_DISPATCH_K(p->K, return (apply_cells_typed<KK>(p, n_cells, h, x, y, alpha, beta, b, s)));
+}
+
+// Diagonal of the cube operator on every copy of n_cells cells of side h (3D, FP64).
+fe_status launch_diag_cells(const fe_problem* p, int64_t n_cells, double h, double* d, hipStream_t s) {
+  const int64_t len = n_cells * p->K * p->K * p->K;
+  if (len == 0) return FE_OK;
+  const double* coef = p->coef64.as<double>();
+  const int64_t nb = (len + 255) / 256;
+  FE_DISPATCH_K(p->K, {
+    hipLaunchKernelGGL((k_diag_cart<double, KK>), dim3((unsigned)nb), dim3(256), 0, s, d, coef + p->co.off_B,
+                       coef + p->co.off_D, h, 3, len);
+    FE_HIP_CHECK(hipGetLastError());
+    return FE_OK;
+  });
+}
+
 }  // namespace fe

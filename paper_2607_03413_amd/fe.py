@@ -102,6 +102,23 @@ _SIGS = {
     "fe_prof_reset": (None, []),
     "fe_prof_query": (_i, [ctypes.c_char_p, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "fe_last_error": (ctypes.c_char_p, []),
+    "fe_adaptive_create": (_i, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "fe_adaptive_destroy": (None, [_vp]),
+    "fe_adaptive_num_levels": (_i, [_vp]),
+    "fe_adaptive_level_cells": (_i64, [_vp, _i]),
+    "fe_adaptive_level_offset": (_i64, [_vp, _i]),
+    "fe_adaptive_active_cells": (_i64, [_vp]),
+    "fe_adaptive_level_info": (_i, [_vp, _i, _vp, _vp]),
+    "fe_adaptive_brick_neighbors": (_i, [_vp, _i, _vp, _vp]),
+    "fe_adaptive_edge_mask": (_i, [_vp, _i, _vp, _vp]),
+    "fe_adaptive_dss": (_i, [_vp, _i, _vp, _i, _vp]),
+    "fe_adaptive_dinv": (_i, [_vp, _i, _vp, _vp]),
+    "fe_adaptive_apply": (_i, [_vp, _vp, _vp, _vp]),
+    "fe_adaptive_prolongate_add": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "fe_adaptive_restrict_add": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
+    "fe_adaptive_rhs_manufactured": (_i, [_vp, _vp, _vp]),
+    "fe_adaptive_precondition": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), _vp]),
+    "fe_adaptive_pcg": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -319,6 +336,111 @@ class Problem:
         rep = PcgReport()
         st = _lib.pcg_solve(self.h, _ptr(b, self.len, "b"), _ptr(x, self.len, "x"), ctypes.byref(opts),
                             ctypes.byref(rep), _stream())
+        if st != 0 and raise_on_error:
+            _check(st)
+        return {"status": STATUS.get(st, st), "iters": rep.iters, "converged": bool(rep.converged),
+                "relres": rep.relres, "energy0": rep.energy0, "energy": rep.energy, "t_setup": rep.t_setup,
+                "t_solve": rep.t_solve}
+
+
+FEATURE_SPHERE, FEATURE_POINT = 0, 1
+
+
+class _AdaptiveDesc(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int), ("global_refinements", ctypes.c_int),
+                ("adaptive_refinements", ctypes.c_int), ("feature", ctypes.c_int),
+                ("center", ctypes.c_double * 3), ("radius", ctypes.c_double), ("band", ctypes.c_double)]
+
+
+class Adaptive:
+    """Owns an fe_adaptive handle: the locally refined hierarchy (see include/fe.h).
+    Vectors of the active mesh are FP64 device tensors in level layout."""
+
+    def __init__(self, degree, global_refinements, adaptive_refinements, feature=FEATURE_SPHERE,
+                 center=(0.5, 0.5, 0.5), radius=0.3125, band=1.0):
+        d = _AdaptiveDesc()
+        d.degree, d.global_refinements, d.adaptive_refinements = degree, global_refinements, adaptive_refinements
+        d.feature, d.radius, d.band = feature, radius, band
+        for a in range(3):
+            d.center[a] = center[a]
+        h = ctypes.c_void_p()
+        _check(_lib.fe_adaptive_create(ctypes.cast(ctypes.pointer(d), ctypes.c_void_p), _stream(), ctypes.byref(h)))
+        self.h = h
+        self.degree, self.K = degree, degree + 1
+        self.n_levels = _lib.fe_adaptive_num_levels(h)
+        self.offsets = [_lib.fe_adaptive_level_offset(h, l) for l in range(self.n_levels + 1)]
+        self.len = self.offsets[-1]
+        self.active_cells = _lib.fe_adaptive_active_cells(h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.fe_adaptive_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_cells(self, level):
+        return _lib.fe_adaptive_level_cells(self.h, level)
+
+    def level_info(self, level):
+        n = self.level_cells(level)
+        coords = np.zeros((n, 3), dtype=np.int32)
+        refined = np.zeros(n, dtype=np.uint8)
+        _check(_lib.fe_adaptive_level_info(self.h, level, coords.ctypes.data_as(ctypes.c_void_p),
+                                           refined.ctypes.data_as(ctypes.c_void_p)))
+        return coords, refined.astype(bool)
+
+    def brick_neighbors(self, level):
+        nb = self.level_cells(level) // 8
+        nbr = np.zeros((nb, 6), dtype=np.int32)
+        par = np.zeros(nb, dtype=np.int32)
+        _check(_lib.fe_adaptive_brick_neighbors(self.h, level, nbr.ctypes.data_as(ctypes.c_void_p),
+                                                par.ctypes.data_as(ctypes.c_void_p)))
+        return nbr, par
+
+    def vec(self):
+        return torch.zeros(self.len, dtype=torch.float64, device="cuda")
+
+    def level_vec(self, level):
+        return torch.zeros(self.offsets[level + 1] - self.offsets[level], dtype=torch.float64, device="cuda")
+
+    def edge_mask(self, level):
+        m = self.level_vec(level)
+        _check(_lib.fe_adaptive_edge_mask(self.h, level, _ptr(m), _stream()))
+        return m
+
+    def dss(self, level, v, averaging=False):
+        _check(_lib.fe_adaptive_dss(self.h, level, _ptr(v), 1 if averaging else 0, _stream()))
+
+    def dinv(self, level):
+        d = self.level_vec(level)
+        _check(_lib.fe_adaptive_dinv(self.h, level, _ptr(d), _stream()))
+        return d
+
+    def apply(self, x, y):
+        _check(_lib.fe_adaptive_apply(self.h, _ptr(x, self.len, "x"), _ptr(y, self.len, "y"), _stream()))
+
+    def prolongate_add(self, fine_level, ec, ef):
+        _check(_lib.fe_adaptive_prolongate_add(self.h, fine_level, _ptr(ec), _ptr(ef), _stream()))
+
+    def restrict_add(self, fine_level, bf, vf, bc):
+        _check(_lib.fe_adaptive_restrict_add(self.h, fine_level, _ptr(bf), _ptr(vf), _ptr(bc), _stream()))
+
+    def rhs_manufactured(self, b):
+        _check(_lib.fe_adaptive_rhs_manufactured(self.h, _ptr(b, self.len, "b"), _stream()))
+
+    def precondition(self, r, z, opts):
+        _check(_lib.fe_adaptive_precondition(self.h, _ptr(r, self.len, "r"), _ptr(z, self.len, "z"),
+                                             ctypes.byref(opts), _stream()))
+
+    def pcg(self, b, x, opts, raise_on_error=True):
+        rep = PcgReport()
+        st = _lib.fe_adaptive_pcg(self.h, _ptr(b, self.len, "b"), _ptr(x, self.len, "x"), ctypes.byref(opts),
+                                  ctypes.byref(rep), _stream())
         if st != 0 and raise_on_error:
             _check(st)
         return {"status": STATUS.get(st, st), "iters": rep.iters, "converged": bool(rep.converged),
