@@ -334,6 +334,75 @@ def bench_paper_cube(fe, n=128, degrees=(2, 3, 4, 5)):
     return out
 
 
+PAPER_ADAPTIVE = {   # Table mg_adaptive_solve_time (Sec. 6.3), cube, A100 80 GB, fp64: context only
+    2: {"cg_iters": 9, "mg_mdofs": 574.2, "solve_mdofs": 52.3},
+    3: {"cg_iters": 9, "mg_mdofs": 992.3, "solve_mdofs": 88.8},
+    4: {"cg_iters": 10, "mg_mdofs": 605.9, "solve_mdofs": 51.8},
+}
+
+
+def bench_paper_adaptive(fe, degrees=(2, 3, 4), depth_degrees=(2, 3, 4, 5)):
+    """Sec. 6.3 on the GPU path: local multigrid (masked Jacobi, omega 0.7, one pre- and one
+    post-sweep) as the CG preconditioner on the cube refined toward a sphere surface (centre
+    (1/2, 1/2, 1/2), radius 5/16, cells within one cell width of it), FP64, CG until <r, M r>
+    has fallen by 1e-14.  (a) Throughput at 6 uniform + 4 adaptive levels (the scale of the
+    paper's deepest cube: ~10^5 -- 10^6 cells on each adaptive level); DoFs as the paper
+    estimates them, active cells x p^3.  (b) Iterations for 1..4 adaptive refinements at 5
+    uniform levels (Table mg_adaptive_iters)."""
+    import torch
+    out = {"throughput": {}, "iterations_vs_depth": {}}
+    opts = fe.default_opts(smoother=fe.SMOOTH_JACOBI, inner=fe.F64, omega=0.7, nu_pre=1, nu_post=1,
+                           stop=1, tol=1e-14, maxit=100)
+    for p in degrees:
+        t0 = time.perf_counter()
+        A = fe.Adaptive(p, 6, 4, fe.FEATURE_SPHERE, (0.5, 0.5, 0.5), 0.3125, 1.0)
+        create_s = time.perf_counter() - t0
+        b = A.vec()
+        A.rhs_manufactured(b)
+        x = A.vec()
+        first = A.pcg(b, x, opts, raise_on_error=False)
+        x.zero_()
+        rep = A.pcg(b, x, opts, raise_on_error=False)
+        z = A.vec()
+        for _ in range(2):
+            A.precondition(b, z, opts)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            A.precondition(b, z, opts)
+        e1.record()
+        torch.cuda.synchronize()
+        vc_s = e0.elapsed_time(e1) / 10 * 1e-3
+        est = A.active_cells * p ** 3
+        rec = {"levels_cells": [A.level_cells(l) for l in range(A.n_levels)], "active_cells": A.active_cells,
+               "dofs_paper_estimate": est, "create_s": create_s, "iters": rep["iters"],
+               "seconds": rep["t_solve"], "first_solve_s": first["t_solve"], "status": rep["status"],
+               "vcycle_s": vc_s, "mg_mdofs": est / vc_s / 1e6, "solve_mdofs": est / rep["t_solve"] / 1e6,
+               "paper_a100": PAPER_ADAPTIVE[p]}
+        log("paper adaptive p=%d: %d active cells, levels %s, setup %.2f s, %d iters, V-cycle %.2f ms (%.0f MDoF/s), "
+            "solve %.4f s (%.0f MDoF/s)" % (p, A.active_cells, rec["levels_cells"], create_s, rep["iters"],
+                                            vc_s * 1e3, rec["mg_mdofs"], rep["t_solve"], rec["solve_mdofs"]))
+        out["throughput"]["p%d" % p] = rec
+        del b, x, z
+        A.close()
+        torch.cuda.empty_cache()
+    for p in depth_degrees:
+        its = []
+        for a in (1, 2, 3, 4):
+            A = fe.Adaptive(p, 5, a, fe.FEATURE_SPHERE, (0.5, 0.5, 0.5), 0.3125, 1.0)
+            b = A.vec()
+            A.rhs_manufactured(b)
+            x = A.vec()
+            its.append(A.pcg(b, x, opts, raise_on_error=False)["iters"])
+            del b, x
+            A.close()
+            torch.cuda.empty_cache()
+        out["iterations_vs_depth"]["p%d" % p] = its
+        log("paper adaptive p=%d: CG iterations for 1..4 adaptive refinements %s" % (p, its))
+    return out
+
+
 def copy_bandwidth():
     """A plain device copy (torch's elementwise copy kernel) over 4 rotated pairs of
     1 GiB buffers: the achievable HBM rate of a streaming kernel in this run, in GB/s
@@ -411,7 +480,7 @@ def main():
         print(json.dumps(bench_deformed_q7(fe)))
         return
     if args.only_paper:
-        print(json.dumps(bench_paper_cube(fe)))
+        print(json.dumps({"cube": bench_paper_cube(fe), "adaptive": bench_paper_adaptive(fe)}))
         return
     if args.only_step and args.step_config != "q3":
         deg, n = (7, 32) if args.step_config.startswith("q7") else (3, 64)
@@ -439,10 +508,12 @@ def main():
     q7_64 = bench_config(fe, 7, 32, torch.float64, max(10, args.steps // 2), args.warmup, nsets=4)
     q7_32 = bench_config(fe, 7, 32, torch.float32, max(10, args.steps // 2), args.warmup, nsets=4)
     pcg = None if args.no_pcg else bench_pcg(fe)
-    paper = None
+    paper = paper_adaptive = None
     if not args.no_paper:
         log("paper's cube solves, p = 2..5 on 128^3 cells")
         paper = bench_paper_cube(fe)
+        log("paper's adaptive cube (local smoothing)")
+        paper_adaptive = bench_paper_adaptive(fe)
     copy_gbs = copy_bandwidth()
     log("plain copy: %.0f GB/s" % copy_gbs)
     deformed = {}
@@ -479,6 +550,7 @@ def main():
                        "unique_dofs": q7_64["n_dofs"]},
         "pcg_q7_32cubed": pcg,
         "paper_cube_128cubed": paper,
+        "paper_adaptive_cube": paper_adaptive,
         "deformed": deformed,
     }
     print(json.dumps(line))
