@@ -411,6 +411,28 @@ fe_status fe_adaptive_precondition(fe_adaptive* a, const double* r, double* z, c
 fe_status fe_adaptive_pcg(fe_adaptive* a, const double* b, double* x, const fe_pcg_opts* opts,
                           fe_pcg_report* report, void* stream);
 
+/* ---- Multi-block meshes: inter-block DSS (Sec. 4.3, Algorithm 8) ----
+ * A 7-block atlas: a centre cube and six caps between its faces and the faces
+ * of the cube of twice its size, each block an n^3 grid of Q_k cells with its
+ * own orientation (block b's lattice axes are permuted and flipped against its
+ * neighbours'; the table is fixed in the library).  Macro-faces join 2 blocks,
+ * macro-lines 2 or 3, macro-vertices 3 or 4.  Layout of a multi-block
+ * cell-wise vector: the 7 blocks in order, each n^3 cells lexicographic,
+ * (k+1)^3 values per cell (x fastest).  Degree 1..8; the vector length must
+ * stay below 2^31 entries. */
+typedef struct fe_multiblock fe_multiblock;
+fe_status fe_multiblock_create(int degree, int n, void* stream, fe_multiblock** out);
+void fe_multiblock_destroy(fe_multiblock* mb);
+int64_t fe_multiblock_len(const fe_multiblock* mb);         /* 7 n^3 (k+1)^3 entries */
+int64_t fe_multiblock_num_nodes(const fe_multiblock* mb);   /* unique DoFs of the glued mesh */
+/* counts[0] macro-face copy pairs, counts[1] macro-line DoFs, counts[2] macro-vertex DoFs. */
+fe_status fe_multiblock_counts(const fe_multiblock* mb, int64_t* counts);
+/* S v = G G^T v in place (averaging = 1: S_bar v, the sum divided by the node's
+ * copy count): the structured cascade inside every block, then the macro-face
+ * pairs, macro-line and macro-vertex passes (one representative copy per
+ * sharing block gathered, the total scattered to every copy). */
+fe_status fe_multiblock_dss(fe_multiblock* mb, void* v, int averaging, fe_dtype dt, void* stream);
+
 /* Thread-local description of the last non-OK status. */
 const char* fe_last_error(void);
 

@@ -119,6 +119,12 @@ _SIGS = {
     "fe_adaptive_rhs_manufactured": (_i, [_vp, _vp, _vp]),
     "fe_adaptive_precondition": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), _vp]),
     "fe_adaptive_pcg": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _vp]),
+    "fe_multiblock_create": (_i, [_i, _i, _vp, ctypes.POINTER(_vp)]),
+    "fe_multiblock_destroy": (None, [_vp]),
+    "fe_multiblock_len": (_i64, [_vp]),
+    "fe_multiblock_num_nodes": (_i64, [_vp]),
+    "fe_multiblock_counts": (_i, [_vp, _vp]),
+    "fe_multiblock_dss": (_i, [_vp, _vp, _i, _i, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -446,6 +452,37 @@ class Adaptive:
         return {"status": STATUS.get(st, st), "iters": rep.iters, "converged": bool(rep.converged),
                 "relres": rep.relres, "energy0": rep.energy0, "energy": rep.energy, "t_setup": rep.t_setup,
                 "t_solve": rep.t_solve}
+
+
+class MultiBlock:
+    """Owns an fe_multiblock handle: the 7-block atlas and its DSS (see include/fe.h)."""
+
+    def __init__(self, degree, n):
+        h = ctypes.c_void_p()
+        _check(_lib.fe_multiblock_create(degree, n, _stream(), ctypes.byref(h)))
+        self.h = h
+        self.degree, self.n = degree, n
+        self.len = _lib.fe_multiblock_len(h)
+        self.n_nodes = _lib.fe_multiblock_num_nodes(h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.fe_multiblock_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def counts(self):
+        c = np.zeros(3, dtype=np.int64)
+        _check(_lib.fe_multiblock_counts(self.h, c.ctypes.data_as(ctypes.c_void_p)))
+        return {"face_pairs": int(c[0]), "line_dofs": int(c[1]), "vertex_dofs": int(c[2])}
+
+    def dss(self, v, averaging=False):
+        _check(_lib.fe_multiblock_dss(self.h, _ptr(v, self.len, "v"), 1 if averaging else 0, _dt(v), _stream()))
 
 
 def set_graphs(on=True):
