@@ -13,6 +13,7 @@ CPU oracle timed on a bounded sample.
     python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-pcg] [--no-cpu]
 """
 import argparse
+import itertools
 import json
 import os
 import sys
@@ -234,10 +235,14 @@ def bench_deformed(fe, k, n, n_train, train_meshes, epochs, with_solve=True, max
     P = fe.Problem(3, k, n, geometry=fe.GEOM_DEFORMED, bc=1, deform_amp=0.1, coef=coefficient_modes(2))
     out["unique_dofs"] = P.n_dofs
     # general apply rate: one (x, y) pair, and 4 rotated pairs (working set beyond the
-    # 256 MB last-level cache: the HBM rate)
-    for dtype, name in ((torch.float64, "fp64"), (torch.float32, "fp32")):
+    # 256 MB last-level cache: the HBM rate); metric stored per Gauss point (6 values
+    # per entry streamed) or formed in the kernel (only the coefficient streamed)
+    for (dtype, name), (mode, mtag) in itertools.product(((torch.float64, "fp64"), (torch.float32, "fp32")),
+                                                         ((0, ""), (1, "_formed_metric"))):
+        P.set_metric_mode(mode)
         s = 8 if dtype == torch.float64 else 4
-        for nsets, tag in ((1, ""), (4, "_rotated4")):
+        geo = 6 if mode == 0 else 1
+        for nsets, tag in ((1, mtag), (4, mtag + "_rotated4")):
             xs = [torch.as_tensor(uniform(P.len, seed=7 + i), dtype=dtype, device="cuda") for i in range(nsets)]
             ys = [P.cellvec(dtype) for _ in range(nsets)]
             for i in range(3):
@@ -251,8 +256,9 @@ def bench_deformed(fe, k, n, n_train, train_meshes, epochs, with_solve=True, max
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 12
             out["apply_" + name + tag] = {"ms": ms, "gdofs": P.n_dofs / ms / 1e6,
-                                          "gbs_algorithmic": (2 * s + 6 * s) * P.len / ms / 1e6}
+                                          "gbs_algorithmic": (2 * s + geo * s) * P.len / ms / 1e6}
             del xs, ys
+    P.set_metric_mode(0)
     # model
     glorot = []
     for i, (no, ni) in enumerate([(64, 64), (64, 64), (12, 64)]):
@@ -282,6 +288,13 @@ def bench_deformed(fe, k, n, n_train, train_meshes, epochs, with_solve=True, max
                                                           factors=2, nu_pre=1, nu_post=1, tol=1e-10)))
         for name, opts in cases:
             out[name] = timed_solve(P, b, opts, "deformed Q%d %d^3 %s" % (k, n, name))
+        # the same learned-factor and plain solves with the metric formed in the kernel
+        P.set_metric_mode(1)
+        for name, opts in cases:
+            if name in ("fp32_chebfdm_learned", "fp64_jacobi_plain"):
+                out[name + "_formed_metric"] = timed_solve(P, b, opts, "deformed Q%d %d^3 %s, formed metric"
+                                                           % (k, n, name))
+        P.set_metric_mode(0)
     P.close()
     torch.cuda.empty_cache()
     return out

@@ -114,6 +114,19 @@ fe_status fe_apply(const fe_problem* prob, const void* x_cell, void* y_cell, fe_
 fe_status fe_apply_level(const fe_problem* prob, int level, const void* x_cell, void* y_cell,
                          fe_dtype dt, void* stream);
 
+/* Geometry traffic of the deformed operator (Sec. 6.4: on curved meshes the
+ * per-point metric terms, not the DoF data, fill the memory bandwidth).
+ * mode 0 (default): the general apply streams the 6 metric entries stored per
+ * Gauss point.  mode 1: it forms the metric in the kernel from the map (the
+ * shift of this geometry is the same separable field in every coordinate, so
+ * J = I / n + 1 (grad S)^T has a closed-form inverse and determinant built
+ * from 1D tables per cell) and streams only the coefficient per point: 1
+ * value instead of 6.  The first switch to mode 1 computes the coefficient
+ * arrays (setup, allocates).  Same operator to rounding; the setup kernels
+ * (diagonal, per-patch factors) keep using the stored metric.  Deformed
+ * geometry only. */
+fe_status fe_set_metric_mode(fe_problem* prob, int mode, void* stream);
+
 /* Vertex-patch additive Schwarz inverse, an admissible smoother of the form
  * P = G P_CG G^T (Sec. 2.1 eq. precond_consistency; Sec. 3.3 and Sec. 4.1
  * name overlapping vertex-patch smoothers as substitutes):

@@ -89,6 +89,8 @@ struct Level {
   double h = 0.0;
   // deformed geometry: per-cell quadrature metric (6 per point), per dtype
   DeviceBuf metric64, metric32;
+  // deformed geometry, metric formed in the apply kernel: coefficient per point, per dtype
+  DeviceBuf kappa64, kappa32;
   // deformed geometry: per-patch 1D eigen-data, per factor mode and dtype
   DeviceBuf patch_eig64[4], patch_eig32[4];
   bool patch_eig_ready[4] = {false, false, false, false};
@@ -135,6 +137,9 @@ struct fe_problem {
   fe::DeviceBuf mlp_params, mlp_adam_m, mlp_adam_v;
   int mlp_ready = 0;
   int64_t mlp_step = 0;
+  // deformed geometry: 1 = the general apply forms the metric from the map
+  // (reads kappa only), 0 = it streams the stored metric (fe_set_metric_mode)
+  int metric_otf = 0;
 };
 
 namespace fe {

@@ -119,6 +119,10 @@ __global__ void __launch_bounds__(1024) k_geometry(const double* __restrict__ ta
     out[cell * K3 + q] = g;
     return;
   }
+  if (mode == 2) {   // the coefficient alone, for the apply that forms the metric itself
+    out[cell * K3 + q] = exp(scale * g);
+    return;
+  }
   // inverse and determinant by cofactors: Jinv = adj(J) / det
   const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
   const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
@@ -172,11 +176,24 @@ __global__ void k_convert_metric(const double* __restrict__ a, T* __restrict__ b
 // General cell-wise apply: y = sum_q grad(phi)^T G_q grad(u) (reference gradients).
 // K^2 threads per cell; forward: z (PHI, DPHI), y (3), x (3) contractions;
 // metric; backward: x (3), y (2 accumulating into 2), z (2 into 1).
-template <typename T, int K>
+//
+// OTF = false: G holds the 6 metric entries per point (setup output).
+// OTF = true (geometry traffic reduced to the coefficient): G holds only
+// kappa at the points, and the metric is formed in the kernel.  The map is
+// X_a = Q_k interpolant of xh_a + S, with the same shift S = amp sx sy sz
+// (s_a = sin(2 pi xh_a)) in every coordinate, so on a cell of side 1/n
+//   J = I / n + 1 v^T,  v_b = dS/dxi_b = amp (products of 1D interpolants of s_a),
+// a rank-one update of a multiple of the identity.  With sigma = 1 + n sum_b v_b:
+// det J = sigma / n^3, J^{-1} = n (I - (n / sigma) 1 v^T), and
+//   G_ab = kappa w_q sigma / n (delta_ab - c (v_a + v_b) + c^2 |v|^2),  c = n / sigma.
+// Per cell the 1D interpolants of s_a and of its derivative at the Gauss
+// points (6K values) are formed once in LDS; nothing of the geometry is read.
+template <typename T, int K, bool OTF = false>
 __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x, T* y,
                                                         const T* __restrict__ G, const T* __restrict__ PHI,
                                                         const T* __restrict__ DPHI, int n, int64_t n_cells,
-                                                        int dirichlet, T alpha, T beta, const T* bsrc) {
+                                                        int dirichlet, T alpha, T beta, const T* bsrc,
+                                                        const double* __restrict__ geo = nullptr, double amp = 0.0) {
   constexpr int TPC = K * K;
   constexpr int CPB = 256 / TPC;
   constexpr int RS = K + 1, PS = K * RS, CS = K * PS;
@@ -185,6 +202,7 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
   __shared__ T s0[CPB * CS];
   __shared__ T s1[CPB * CS];
   __shared__ T s2[CPB * CS];
+  __shared__ double sg[OTF ? CPB * 9 * K : 1];   // per cell: s_a at the nodes (3K), interpolants (3K), derivatives (3K)
   const int tid = threadIdx.x;
   const int c = tid / TPC;
   const int p = tid - c * TPC;
@@ -196,6 +214,25 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
   T* l0 = s0 + c * CS;
   T* l1 = s1 + c * CS;
   T* l2 = s2 + c * CS;
+  if (OTF) {
+    // 1D tables of the shift field: s_a(node i), then its interpolant and
+    // derivative at Gauss point q (geo: FP64 PHI, DPHI, WQ, XQ, XN tables)
+    double* g = sg + c * 9 * K;
+    const int cc[3] = {cx, cy, cz};
+    for (int t = p; t < 3 * K; t += TPC) {
+      const int a = t / K, i = t - a * K;
+      g[t] = sin(2.0 * M_PI * ((cc[a] + geo[2 * K * K + 2 * K + i]) / n));
+    }
+    __syncthreads();
+    for (int t = p; t < 6 * K; t += TPC) {
+      const int which = t / (3 * K), r = t - which * 3 * K, a = r / K, q = r - a * K;
+      const double* M = geo + which * K * K + q * K;
+      double s = 0.0;
+      for (int i = 0; i < K; ++i) s = fma(M[i], g[a * K + i], s);
+      g[3 * K + t] = s;   // [3K + a K + q]: interpolant; [6K + a K + q]: derivative
+    }
+    __syncthreads();
+  }
   uint32_t zmask = 0;
   if (dirichlet && active) {
     const bool mxy = on_boundary(cx, p0, n, k) || on_boundary(cy, p1, n, k);
@@ -241,7 +278,31 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
   pencil_mv<T, K>(DPHI, v, gx);   // d/dxi   = DPHI_x PHI_y PHI_z u
   pencil_mv<T, K>(PHI, w, gy);    // d/deta  = PHI_x DPHI_y PHI_z u
   pencil_mv<T, K>(PHI, b, gz);    // d/dzeta = PHI_x PHI_y DPHI_z u
-  if (active) {
+  if (active && OTF) {
+    const T* kc = G + cell * K3 + K * (p0 + K * p1);
+    const double* g = sg + c * 9 * K;
+    const double* WQ = geo + 2 * K * K;
+    const T Ay = (T)(amp * g[3 * K + K + p0]), By = (T)(amp * g[6 * K + K + p0]);
+    const T Az = (T)g[3 * K + 2 * K + p1], Bz = (T)g[6 * K + 2 * K + p1];
+    const T wyz = (T)(WQ[p0] * WQ[p1]);
+    const T nn = (T)n;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const T Ax = (T)g[3 * K + q], Bx = (T)g[6 * K + q];
+      const T v0 = Bx * Ay * Az, v1 = Ax * By * Az, v2 = Ax * Ay * Bz;
+      const T sigma = T(1) + nn * (v0 + v1 + v2);
+      const T cq = nn / sigma;
+      const T vv = cq * cq * (v0 * v0 + v1 * v1 + v2 * v2);
+      const T f = kc[q] * (T)WQ[q] * wyz * sigma / nn;
+      const T gxx = f * (T(1) - 2 * cq * v0 + vv), gyy = f * (T(1) - 2 * cq * v1 + vv);
+      const T gzz = f * (T(1) - 2 * cq * v2 + vv);
+      const T gxy = f * (vv - cq * (v0 + v1)), gxz = f * (vv - cq * (v0 + v2)), gyz = f * (vv - cq * (v1 + v2));
+      const T fx = gxx * gx[q] + gxy * gy[q] + gxz * gz[q];
+      const T fy = gxy * gx[q] + gyy * gy[q] + gyz * gz[q];
+      const T fz = gxz * gx[q] + gyz * gy[q] + gzz * gz[q];
+      gx[q] = fx; gy[q] = fy; gz[q] = fz;
+    }
+  } else if (active) {
     const T* Gc = G + cell * 6 * K3 + K * (p0 + K * p1);
 #pragma unroll
     for (int q = 0; q < K; ++q) {
@@ -464,9 +525,17 @@ static fe_status apply_general_typed(const fe_problem* p, const Level& L, const 
                                      const T* tab, T alpha, T beta, const T* b, hipStream_t s) {
   constexpr int CPB = 256 / (K * K);
   const unsigned nb = (unsigned)((L.n_cells + CPB - 1) / CPB);
-  ProfScope ps("apply_general", s);
-  hipLaunchKernelGGL((k_apply_general3<T, K>), dim3(nb), dim3(CPB * K * K), 0, s, x, y, G, tab, tab + K * K, L.n,
-                     L.n_cells, p->bc, alpha, beta, b);
+  if (p->metric_otf) {
+    ProfScope ps("apply_general_otf", s);
+    const T* kap = sizeof(T) == 8 ? (const T*)L.kappa64.p : (const T*)L.kappa32.p;
+    hipLaunchKernelGGL((k_apply_general3<T, K, true>), dim3(nb), dim3(CPB * K * K), 0, s, x, y, kap, tab,
+                       tab + K * K, L.n, L.n_cells, p->bc, alpha, beta, b, p->geo_tab64.as<double>(),
+                       p->desc.deform_amp);
+  } else {
+    ProfScope ps("apply_general", s);
+    hipLaunchKernelGGL((k_apply_general3<T, K, false>), dim3(nb), dim3(CPB * K * K), 0, s, x, y, G, tab,
+                       tab + K * K, L.n, L.n_cells, p->bc, alpha, beta, b, nullptr, 0.0);
+  }
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
 }
@@ -483,6 +552,50 @@ fe_status launch_apply_general(const fe_problem* p, int level, const void* x, vo
                                                              L.metric32.as<float>(), p->geo_tab32.as<float>(),
                                                              (float)alpha, (float)beta, (const float*)b, s)));
 }
+
+// Coefficient kappa at the Gauss points of every level (both dtypes), for the
+// apply that forms the metric itself.
+template <int K>
+static fe_status kappa_typed(fe_problem* p, hipStream_t s) {
+  constexpr int K3 = K * K * K;
+  const int nm = (int)p->amp.size();
+  std::vector<double> md(2 * nm + 1, 0.0);
+  for (int j = 0; j < nm; ++j) { md[j] = p->amp[j]; md[nm + j] = p->phase[j]; }
+  DeviceBuf dmodes;
+  FE_CHECK(dmodes.alloc(md.size() * sizeof(double) + 3 * nm * sizeof(int32_t) + 64));
+  double* damp = dmodes.as<double>();
+  int* dm = reinterpret_cast<int*>(damp + md.size());
+  FE_HIP_CHECK(hipMemcpyAsync(damp, md.data(), md.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (nm > 0) FE_HIP_CHECK(hipMemcpyAsync(dm, p->modes.data(), 3 * nm * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  for (Level& L : p->levels) {
+    const int64_t n = L.n_cells * K3;
+    FE_CHECK(L.kappa64.alloc(n * sizeof(double)));
+    FE_CHECK(L.kappa32.alloc(n * sizeof(float)));
+    hipLaunchKernelGGL((k_geometry<K>), dim3((unsigned)L.n_cells), dim3(K3), 0, s, p->geo_tab64.as<double>(), L.n,
+                       p->desc.deform_amp, dm, damp, damp + nm, nm, p->coef_scale, 2, L.kappa64.as<double>());
+    FE_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((k_convert_metric<float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       L.kappa64.as<double>(), L.kappa32.as<float>(), n);
+    FE_HIP_CHECK(hipGetLastError());
+  }
+  FE_HIP_CHECK(hipStreamSynchronize(s));
+  return FE_OK;
+}
+
+}  // namespace fe
+
+extern "C" fe_status fe_set_metric_mode(fe_problem* p, int mode, void* stream) {
+  using namespace fe;
+  if (!p) return fail(FE_EINVAL, "null problem");
+  if (mode != 0 && mode != 1) return fail(FE_EINVAL, "metric mode must be 0 or 1");
+  if (mode == 1 && p->desc.geometry != FE_GEOM_DEFORMED)
+    return fail(FE_EINVAL, "the metric is formed in the kernel for the deformed geometry only");
+  if (mode == 1 && !p->levels.back().kappa64.p) FE_DISPATCH_K(p->K, FE_CHECK(kappa_typed<KK>(p, (hipStream_t)stream)); break);
+  p->metric_otf = mode;
+  return FE_OK;
+}
+
+namespace fe {
 
 template <int K>
 static fe_status diag_general_typed(const fe_problem* p, const Level& L, double* d, hipStream_t s) {

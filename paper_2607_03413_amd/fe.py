@@ -119,6 +119,7 @@ _SIGS = {
     "fe_adaptive_rhs_manufactured": (_i, [_vp, _vp, _vp]),
     "fe_adaptive_precondition": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), _vp]),
     "fe_adaptive_pcg": (_i, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _vp]),
+    "fe_set_metric_mode": (_i, [_vp, _i, _vp]),
     "fe_multiblock_create": (_i, [_i, _i, _vp, ctypes.POINTER(_vp)]),
     "fe_multiblock_destroy": (None, [_vp]),
     "fe_multiblock_len": (_i64, [_vp]),
@@ -238,6 +239,10 @@ class Problem:
     def patch_inverse(self, r, z, factors=0, level=-1):
         _check(_lib.patch_fdm_inverse_level(self.h, level, _ptr(r, name="r"), _ptr(z, name="z"), _dt(r), factors,
                                             _stream()))
+
+    def set_metric_mode(self, mode):
+        """0: the deformed operator streams the stored metric; 1: it forms the metric in the kernel."""
+        _check(_lib.fe_set_metric_mode(self.h, int(mode), _stream()))
 
     def patch_prepare(self, dtype=torch.float64, factors=0, level=-1):
         _check(_lib.fe_patch_prepare(self.h, level, F64 if dtype == torch.float64 else F32, factors, _stream()))

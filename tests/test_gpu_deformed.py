@@ -34,11 +34,15 @@ def problem(fe, k, n, bc=1, seed=2):
 
 @pytest.mark.parametrize("k,n", [(1, 4), (2, 3), (3, 4), (7, 2)])
 @pytest.mark.parametrize("bc", [0, 1])
-def test_general_apply(gpu_lib, k, n, bc):
+@pytest.mark.parametrize("metric", [0, 1])
+def test_general_apply(gpu_lib, k, n, bc, metric):
+    """metric = 0: the stored metric per Gauss point; metric = 1: the metric formed
+    in the kernel from the map (only the coefficient is read)."""
     fe = gpu_lib
     m = StructuredMesh(3, k, n)
     g = DeformedGeometry(m, AMP, coefficient_modes(2))
     P = problem(fe, k, n, bc)
+    P.set_metric_mode(metric)
     x = m.gather(uniform(m.n_global, seed=300)).ravel()
     if bc:
         mask = boundary_mask_cellwise(m).ravel()
@@ -50,6 +54,28 @@ def test_general_apply(gpu_lib, k, n, bc):
         y = P.cellvec(dtype)
         P.apply(dev(x, dtype), y)
         assert relerr(host(y), expect) < tol, (dtype, relerr(host(y), expect))
+        # entry-wise: no entry off by more than the tolerance times the largest entry
+        assert np.max(np.abs(host(y) - expect)) <= 10 * tol * np.max(np.abs(expect)), dtype
+
+
+def test_formed_metric_solve_matches_stored_metric(gpu_lib):
+    """The MG-PCG solve with the metric formed in the kernel takes the iterations of
+    the stored-metric solve and reaches the same solution."""
+    fe = gpu_lib
+    P = problem(fe, 3, 8)
+    b = P.cellvec()
+    P.rhs_manufactured(b)
+    opts = fe.default_opts(smoother=fe.SMOOTH_CHEB_FDM, inner=fe.F32, flexible=1, factors=1, nu_pre=1, nu_post=1,
+                           tol=1e-10)
+    x0 = P.cellvec()
+    r0 = P.pcg_solve(b, x0, opts)
+    P.set_metric_mode(1)
+    x1 = P.cellvec()
+    r1 = P.pcg_solve(b, x1, opts)
+    assert r0["converged"] and r1["converged"] and abs(r0["iters"] - r1["iters"]) <= 1
+    assert relerr(host(x1), host(x0)) < 1e-8
+    with pytest.raises(fe.FeError):
+        fe.Problem(3, 3, 4, bc=1).set_metric_mode(1)
 
 
 @pytest.mark.parametrize("k,n", [(2, 3), (3, 2)])
