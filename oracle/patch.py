@@ -78,6 +78,31 @@ def patch_inverse_global(A_csr, mesh, r_global, shared=False):
     return z
 
 
+def patch_inverse_cartesian(mesh, r_cell):
+    """z = G sum_p R_p^T A_p^{-1} R_p G^T r on a uniform Cartesian mesh of any size.
+
+    Every interior patch matrix is then the same (translation invariance; the
+    patch interiors never touch the boundary), so A_p is taken from the one
+    interior vertex of a 2^d mesh with the same element matrix, inverted once
+    (Cholesky) and applied to all patches as one dense product.
+    """
+    from .mesh import StructuredMesh
+    from .operators import assemble_csr, element_matrix_cartesian
+    small = StructuredMesh(mesh.dim, mesh.k, 2)
+    A_small = assemble_csr(small, element_matrix_cartesian(mesh.dim, mesh.k, mesh.h))
+    i0 = patch_dof_indices(small)[0]
+    Ap = A_small[i0][:, i0].toarray()
+    Ainv = sla.cho_solve(sla.cho_factor(Ap), np.eye(Ap.shape[0]))
+    idx = patch_dof_indices(mesh)
+    r_global = mesh.assemble(r_cell)
+    z = np.zeros_like(r_global)
+    if idx.shape[0]:
+        W = r_global[idx] @ Ainv.T
+        for j in range(idx.shape[1]):      # for one local offset the patches' DoFs are distinct
+            z[idx[:, j]] += W[:, j]
+    return mesh.gather(z)
+
+
 def patch_inverse_cellwise(A_csr, mesh, r_cell, shared=False):
     """z = G sum_p R_p^T A_p^{-1} R_p G^T r (dual cell-wise in, primal cell-wise out)."""
     r_global = mesh.assemble(r_cell)

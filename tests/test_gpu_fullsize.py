@@ -15,6 +15,9 @@ The oracle cannot form these operators whole, so it checks outputs one by one:
 Inputs are seeded synthetic vectors (synthetic_inputs); nothing expected comes
 from the GPU path.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -42,6 +45,17 @@ def host(t):
 
 def relerr(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+ENTRY_TOL = {torch.float64: 1e-11, torch.float32: 1e-4}
+
+
+def assert_close(got, expect, dtype, tol):
+    """Norm-wise relative error below tol and max |got - exp| <= c max |exp|."""
+    rel = relerr(got, expect)
+    ent = np.max(np.abs(got - expect)) / max(np.max(np.abs(expect)), 1e-300)
+    assert rel < tol, (dtype, rel)
+    assert ent < ENTRY_TOL[dtype], (dtype, ent)
 
 
 def sample_cells(n, count, seed):
@@ -125,7 +139,7 @@ def test_apply_full_size(gpu_lib, k, n):
         y = P.cellvec(dtype)
         P.apply(dev(x, dtype), y)
         got = host(y).reshape(m.n_cells, -1)[cells]
-        assert relerr(got, expect) < tol, (dtype, relerr(got, expect))
+        assert_close(got, expect, dtype, tol)
     P.close()
 
 
@@ -141,7 +155,7 @@ def test_patch_inverse_full_size(gpu_lib, k, n):
         z = P.cellvec(dtype)
         P.patch_inverse(dev(r, dtype), z)
         got = host(z).reshape(m.n_cells, -1)[cells]
-        assert relerr(got, expect) < tol, (dtype, relerr(got, expect))
+        assert_close(got, expect, dtype, tol)
     P.close()
 
 
@@ -169,23 +183,33 @@ def test_patch_inverse_tile_seams(gpu_lib, n):
         P.patch_inverse(dev(r, dtype), z)
         zh = host(z)
         got = zh.reshape(m.n_cells, -1)[cells]
-        assert relerr(got, expect) < tol, (dtype, relerr(got, expect))
+        assert_close(got, expect, dtype, tol)
         first = np.full(m.n_global, np.nan)
         first[idx[::-1]] = zh[::-1]
         assert np.array_equal(zh, first[idx])
     P.close()
 
 
-@pytest.mark.parametrize("k,n,with_coef", [(3, 48, True), (7, 64, False)])
-def test_general_apply_full_size(gpu_lib, k, n, with_coef):
-    """Q3 48^3 with the coefficient field of the benchmark; Q7 64^3 deformed with
-    kappa = 1 (the coefficient's whole-mesh rescaling at that size is beyond the
-    oracle's time budget; the coefficient only enters the setup kernels)."""
+def cached_coefficient_scale(k, n, amp, seed):
+    """The whole-mesh coefficient scale, written by tests/golden/make_coef_scale.py
+    (which calls only the oracle); recomputed by the oracle when not listed."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "coef_scale.json")
+    with open(path) as f:
+        scales = json.load(f)["scales"]
+    key = "%d_%d_%g_%d" % (k, n, amp, seed)
+    if key in scales:
+        return scales[key]
+    return coefficient_scale(StructuredMesh(3, k, n), amp, coefficient_modes(seed))
+
+
+@pytest.mark.parametrize("k,n", [(3, 48), (7, 64)])
+def test_general_apply_full_size(gpu_lib, k, n):
+    """The deformed benchmark meshes with the benchmark's coefficient field."""
     fe = gpu_lib
     amp = 0.1
     m = StructuredMesh(3, k, n)
-    coef = coefficient_modes(2) if with_coef else None
-    scale = coefficient_scale(m, amp, coef) if with_coef else None
+    coef = coefficient_modes(2)
+    scale = cached_coefficient_scale(k, n, amp, 2)
     cells = sample_cells(n, 24, seed=205)
     g = DeformedGeometry(m, amp, coef, scale=scale, cells=cells)
     x = uniform(m.n_cellwise, seed=7).reshape(m.n_cells, -1)
@@ -196,7 +220,7 @@ def test_general_apply_full_size(gpu_lib, k, n, with_coef):
         y = P.cellvec(dtype)
         P.apply(dev(x, dtype), y)
         got = host(y).reshape(m.n_cells, -1)[cells]
-        assert relerr(got, expect) < tol, (dtype, relerr(got, expect))
+        assert_close(got, expect, dtype, tol)
     P.close()
 
 

@@ -77,6 +77,36 @@ def test_best_fit_patch_inverse(gpu_lib, k, n):
         assert relerr(host(z), expect) < tol, (dtype, relerr(host(z), expect))
 
 
+@pytest.mark.parametrize("k,n", [(2, 4), (3, 3)])
+def test_learned_patch_inverse(gpu_lib, k, n):
+    """factors = 2: the patch inverse with the factors the model predicts equals the
+    oracle's separable inverse with weights exp(forward(features) + log(h) / 3).
+    The prediction is an FP32 network on both paths' inputs, so the bound is the
+    FP32 forward's rounding (about 1e-7 in each log-weight of size 0.4, summed
+    over 64-term products) carried through the inverse, not FP64 rounding."""
+    from oracle.learned import weights_from_targets
+    from oracle.sepfit import sep_patch_inverse_cellwise
+    fe = gpu_lib
+    m = StructuredMesh(3, k, n)
+    modes, amps, phases = coefficient_modes(2)
+    g = DeformedGeometry(m, AMP, (modes, amps, phases))
+    params = init_params(40)
+    params[-(12 * 64 + 12):] *= 0.3          # log-weights of moderate size
+    params32 = params.astype(np.float32).astype(np.float64)
+    w = weights_from_targets(forward(params32, patch_features(g, modes, amps, phases))[0], m.h)
+    r = uniform(m.n_cellwise, seed=313)
+    expect = sep_patch_inverse_cellwise(m, w, r.reshape(m.n_cells, -1)).ravel()
+    P = problem(fe, k, n)
+    P.mlp_set_params(torch.as_tensor(params32, dtype=torch.float32, device="cuda"))
+    for dtype, tol in ((torch.float64, 1e-6), (torch.float32, 2e-6)):
+        z = P.cellvec(dtype)
+        P.patch_inverse(torch.as_tensor(r, dtype=dtype, device="cuda"), z, factors=2)
+        got = host(z)
+        print("learned patch inverse Q%d %d^3 %s: %.2e" % (k, n, dtype, relerr(got, expect)), flush=True)
+        assert relerr(got, expect) < tol, (dtype, relerr(got, expect))
+    P.close()
+
+
 def test_mlp_forward_gradient_and_adam(gpu_lib):
     fe = gpu_lib
     assert fe.MLP_PARAMS == N_PARAMS

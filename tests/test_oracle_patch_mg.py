@@ -190,3 +190,16 @@ def test_chebyshev_patch_smoother_vcycle():
     M = lambda r: vcycle(h, r, sm)
     rate = _contraction(h, M, h.levels[-1].A, cycles=8)
     assert rate < 0.25, rate
+
+
+@pytest.mark.parametrize("dim,k,n", [(2, 2, 5), (3, 2, 4), (3, 3, 3)])
+def test_batched_cartesian_patch_inverse_is_the_dense_definition(dim, k, n):
+    """The batched form used at full size (one shared A_p from a 2^d mesh of the same
+    cell size) equals the per-patch dense Cholesky of R_p A_CG R_p^T."""
+    from oracle.patch import patch_inverse_cartesian
+    m = StructuredMesh(dim, k, n)
+    A = assemble_csr(m, element_matrix_cartesian(dim, k, m.h))
+    r = uniform(m.n_cellwise, seed=31).reshape(m.n_cells, -1)
+    a = patch_inverse_cartesian(m, r)
+    b = patch_inverse_cellwise(A, m, r, shared=False)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))

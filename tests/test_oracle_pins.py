@@ -189,3 +189,22 @@ def test_features_on_an_affine_mesh(k, n):
     assert f.shape[0] == (n - 1) ** 3
     assert np.max(np.abs(f - expect[None, None, :])) < 1e-13
     assert min(abs(C[0, 1]), abs(C[0, 2]), abs(C[1, 2])) > 1e-2
+
+
+def test_cached_coefficient_scale_is_the_oracles():
+    """The cached whole-mesh coefficient scales are what the oracle computes (the
+    Q3 48^3 entry is recomputed here; both come from the same committed script)."""
+    import json
+    import os
+    from oracle.geometry import coefficient_scale
+    from oracle.mesh import StructuredMesh
+    from synthetic_inputs import coefficient_modes
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "coef_scale.json")
+    with open(path) as f:
+        scales = json.load(f)["scales"]
+    assert set(scales) == {"3_48_0.1_2", "7_64_0.1_2"}
+    s = coefficient_scale(StructuredMesh(3, 3, 48), 0.1, coefficient_modes(2), chunk=512)
+    assert s == scales["3_48_0.1_2"]
+    # |g| <= sum |a_j|, so s >= 1 / sum |a_j|; the finer mesh samples the same field
+    assert all(v >= 1.0 / np.sum(np.abs(coefficient_modes(2)[1])) for v in scales.values())
+    assert abs(scales["7_64_0.1_2"] - s) < 1e-3 * s
