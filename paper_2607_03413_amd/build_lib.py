@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfe.so")
 SOURCES = ["fe_api.cpp", "solver.cpp", "basis1d.cpp", "k_apply.hip", "k_dss.hip", "k_fdm.hip", "k_mg.hip",
-           "k_general.hip", "k_mlp.hip", "k_smooth.hip", "k_fdm_fused.hip", "k_fdm_wave.hip",
+           "k_general.hip", "k_mlp.hip", "k_smooth.hip", "k_fdm_fused.hip", "k_fdm_lattice.hip", "k_fdm_wave.hip",
            "fe_noalloc.hip", "adaptive.cpp", "k_adapt.hip",
            "multiblock.cpp", "k_multiblock.hip"]
 ARCH = os.environ.get("FE_OFFLOAD_ARCH", "gfx950")

@@ -1116,8 +1116,11 @@ static fe_status split_typed(const fe_problem* p, int li, const T* r, T* z, cons
   return FE_OK;
 }
 
+fe_status launch_patch_lattice(const fe_problem* p, int level, const void* r, void* z, fe_dtype dt, hipStream_t s);
+
 fe_status launch_patch_fused(const fe_problem* p, int level, const void* r, void* z, fe_dtype dt, hipStream_t s) {
   const int li = level < 0 ? (int)p->levels.size() - 1 : level;
+  if (p->K == 4 && p->levels[li].n >= 2) return launch_patch_lattice(p, li, r, z, dt, s);
   if (dt == FE_F64) {
     if (p->K == 3) return fused_typed<double, 3>(p, li, (const double*)r, (double*)z, p->coef64.as<double>(), s);
     if (p->K == 4 && p->levels[li].n >= 2)

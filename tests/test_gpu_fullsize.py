@@ -159,19 +159,20 @@ def test_patch_inverse_full_size(gpu_lib, k, n):
     P.close()
 
 
-@pytest.mark.parametrize("n", [2, 33, 34, 40])
+@pytest.mark.parametrize("n", [2, 11, 16, 17, 30, 31, 33, 34, 40])
 def test_patch_inverse_tile_seams(gpu_lib, n):
     """Q3 at sizes that place the x-tile, y-tile and z-chunk seams of the
-    blocked kernels differently (one x-tile; 32 patches in a row; a last x-tile
-    that mostly overlaps the first; a partial last tile): sampled cells on and
-    next to every seam against the oracle, and bit-identical copies everywhere."""
+    blocked kernel differently (one tile; a tile exactly full; one patch more;
+    a last tile that mostly overlaps the one before; a partial last tile;
+    tiles of 15 x 10 patches owning 14 x 9 cells): sampled cells on and next to
+    every seam against the oracle, and bit-identical copies everywhere."""
     fe = gpu_lib
     k = 3
     m = StructuredMesh(3, k, n)
     r = uniform(m.n_cellwise, seed=206)
     g = rng(207)
-    xs = sorted({c for c in (0, 1, 29, 30, 31, 32, 33, n - 2, n - 1) if 0 <= c < n})
-    ys = sorted({c for c in (0, 6, 7, 8, 13, 14, n - 2, n - 1) if 0 <= c < n})
+    xs = sorted({c for c in (0, 1, 13, 14, 15, 16, 27, 28, 29, 30, 31, 32, 33, n - 2, n - 1) if 0 <= c < n})
+    ys = sorted({c for c in (0, 1, 8, 9, 10, 17, 18, 19, 27, 28, n - 2, n - 1) if 0 <= c < n})
     cells = {x + n * (y + n * int(g.integers(0, n))) for x in xs for y in ys}
     cells |= {x + n * (y + n * z) for x in xs for y in (0, n - 1) for z in (0, n - 1)}
     cells = np.array(sorted(cells), dtype=np.int64)
