@@ -45,7 +45,9 @@
 // layer C1-1 (and level C0's lower planes are the chunk below's).
 //
 // The next level's input rows are loaded into registers while the current
-// level computes; the stores of a level are not waited for.
+// level computes, and waited for at the end of the level, before its stores
+// are issued (with one counter for loads and stores, a later wait for loads
+// would wait for the stores too); the stores are not waited for.
 #include "fe_internal.h"
 #include "kernel_common.h"
 
@@ -135,7 +137,7 @@ __device__ __forceinline__ void store_row(T* __restrict__ p, T a, T b, T c, T d)
 
 }  // namespace
 
-template <typename T>
+template <typename T, bool YFULL>
 __global__ void __launch_bounds__(kLThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
                                                             const T* __restrict__ Seo, const T* __restrict__ il,
@@ -177,10 +179,11 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
 
   // the y pass's inverse eigenvalue sums for its (z-mode, x-mode)
   const int yj = tid / kLCols, ycol = tid - yj * kLCols, ypx = ycol / 5, yix = ycol - 5 * (ycol / 5);
+  // (zero for windows of patches beyond the mesh, x > n-1)
   T ily[5];
+  const bool ypx_ok = tid < kLYTasks && X0 + ypx <= n - 1;
 #pragma unroll
-  for (int a = 0; a < 5; ++a) ily[a] = tid < kLYTasks ? il[(yj * 5 + a) * 5 + yix] : T(0);
-  const bool ypx_ok = X0 + ypx <= n - 1;
+  for (int a = 0; a < 5; ++a) ily[a] = ypx_ok ? il[(yj * 5 + a) * 5 + yix] : T(0);
 
   // input rows of one z-plane (own row and, in copy rows, row 3 of the cell row below)
   auto load_plane = [&](int lz, int iz, Row4<T>& a, Row4<T>& b) {
@@ -277,7 +280,9 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
                           col[(m0 + 3) * kLCols], col[(m0 + 4) * kLCols]};
           T y[5], w[5];
           fwd5(x, y, SE, SO);
-          const bool ok = ypx_ok && Y0 + py <= n - 1;
+          // (rows of patches beyond the mesh, y > n-1, exist only when the tile
+          // is larger than the mesh)
+          const bool ok = YFULL || Y0 + py <= n - 1;
 #pragma unroll
           for (int a = 0; a < 5; ++a) y[a] = ok ? y[a] * ily[a] : T(0);
           bwd5(y, w, SE, SO);
@@ -337,6 +342,10 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
       if (m == kLRows - 1 && own_x && own_y && cy == n - 1)
         store_row(z + zoff + (row_off + 4), T(0), T(0), T(0), T(0));
     };
+    // The next level's rows have had the whole level to arrive: wait for them
+    // here, before the stores, so that the wait at the next level's gather is
+    // not also a wait for these stores.
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     if (vz - 1 >= C0) {
       store_plane(vz - 1, 1, w1);
       store_plane(vz - 1, 2, w2);
@@ -366,7 +375,7 @@ static fe_status lattice_typed(const fe_problem* p, int li, const T* r, T* z, co
     int dev = 0, cus = 0, per_cu = 0;
     FE_HIP_CHECK(hipGetDevice(&dev));
     FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fdm_lattice3<T>, kLThreads, 0));
+    FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fdm_lattice3<T, true>, kLThreads, 0));
     resident = cus * (per_cu > 0 ? per_cu : 1);
   }
   // z-chunk length that minimizes (rounds of blocks) x (levels per block)
@@ -382,7 +391,12 @@ static fe_status lattice_typed(const fe_problem* p, int li, const T* r, T* z, co
   const T* Seo = coef + p->co.off_Seo;
   const T* il = coef + p->co.off_il + (int64_t)li * 125;
   ProfScope ps("fdm_lattice", s);
-  hipLaunchKernelGGL(k_fdm_lattice3<T>, dim3((unsigned)blocks), dim3(kLThreads), 0, s, r, z, Seo, il, n, nxt, nyt, len);
+  if (n > kLPY)   // every tile's patch rows are in the mesh
+    hipLaunchKernelGGL((k_fdm_lattice3<T, true>), dim3((unsigned)blocks), dim3(kLThreads), 0, s, r, z, Seo, il, n, nxt,
+                       nyt, len);
+  else
+    hipLaunchKernelGGL((k_fdm_lattice3<T, false>), dim3((unsigned)blocks), dim3(kLThreads), 0, s, r, z, Seo, il, n, nxt,
+                       nyt, len);
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
 }
