@@ -98,7 +98,7 @@ def kernel_times(fe, P, sets, reps):
     torch.cuda.synchronize()
     fe.prof_enable(False)
     out = {}
-    for name in ("apply", "fdm_patch", "fdm_sum", "fdm_fused"):
+    for name in ("apply", "fdm_patch", "fdm_sum", "fdm_fused", "fdm_lattice"):
         c, t = fe.prof_query(name)
         if c:
             out[name] = t / c
@@ -148,8 +148,9 @@ def kernel_bytes(P, dt_bytes):
     # patch solutions: k <= 3 split by cell slot (8 blocks of k^3 per patch),
     # k >= 4 patch-major ((2k-1)^3 per patch)
     wbuf = n_patches * (8 * k ** 3 if k <= 3 else (2 * k - 1) ** 3) * dt_bytes
-    # the fused patch inverse reads r and writes z once
-    return {"apply": 2 * vec, "fdm_patch": vec + wbuf, "fdm_sum": wbuf + vec, "fdm_fused": 2 * vec}
+    # the fused (k = 2) and lattice (k = 3) patch inverses read r and write z once
+    return {"apply": 2 * vec, "fdm_patch": vec + wbuf, "fdm_sum": wbuf + vec, "fdm_fused": 2 * vec,
+            "fdm_lattice": 2 * vec}
 
 
 def bench_config(fe, degree, n, dtype, steps, warmup, nsets):
