@@ -10,7 +10,7 @@
 //
 // Instead of one thread per patch (all 125 patch values in registers, each
 // patch transformed on its own), the transforms are applied to the lattice
-// of a tile of 15 x 10 patches, one patch level vz at a time, marching up in
+// of a tile of 7 x 10 patches, one patch level vz at a time, marching up in
 // z:
 //   * z: each lattice column (x, y node) forms its 5 z-values once (the
 //     vertex plane sums its two copies) and takes them to the 5 z-modes; the
@@ -27,9 +27,11 @@
 //     (the 2 upper planes are kept as partial sums for the next level).
 // The x-modes sit in LDS between the x and y passes (one array for the whole
 // level); all other values stay in registers.  A thread owns the nodes 0..2
-// of one cell along x in one lattice row: lanes are cells along x (one
-// 16-lane DPP row per lattice row), the 32 lattice rows are the 32 DPP rows
-// of the 512-thread block.
+// of one cell along x in one lattice row: 8 lanes are the cells X0-1 ..
+// X0+6 of a row, the 32 lattice rows make a 256-thread block.  Narrow tiles
+// keep the x-modes of a block at 45 KB (FP64), so that two blocks share a
+// compute unit and one's memory phase overlaps the other's compute (15
+// patches per row, one block per CU: 124 against 113 us FP64 at 64^3).
 //
 // Every node is summed in a fixed order (lower window first along each axis;
 // in z the partial sums of the level below first), and every copy of a node
@@ -37,8 +39,8 @@
 // two tiles both compute (the tiles overlap by one patch) are computed by the
 // same arithmetic in both.
 //
-// Tiles: tile t along x has patches X0 .. X0+14 and owns the cells X0 ..
-// X0+13 (the first also cell 0, the last everything up to n-1; the last tile
+// Tiles: tile t along x has patches X0 .. X0+6 and owns the cells X0 ..
+// X0+5 (the first also cell 0, the last everything up to n-1; the last tile
 // is shifted down so that it ends at patch n-1).  Along y, 10 patches and 9
 // cells.  Along z the mesh is cut into chunks of levels C0 .. C1; a chunk owns
 // the cell layers C0 .. C1-1 and computes level C1 for the upper planes of
@@ -55,15 +57,21 @@ namespace fe {
 
 namespace {
 
-constexpr int kLPX = 15;                  // patches per tile along x (lanes 1..15)
+constexpr int kLPX = 7;                   // patches per tile along x (lanes 1..7)
+constexpr int kLX = kLPX + 1;             // lanes per lattice row (cells X0-1 .. X0+6)
 constexpr int kLPY = 10;                  // patches per tile along y
 constexpr int kLRows = 3 * (kLPY + 1) - 1;  // lattice rows per tile (32)
-constexpr int kLThreads = 16 * kLRows;      // 512: one 16-lane DPP row per lattice row
-constexpr int kLCols = kLPX * 5;            // (patch column, x-mode) pairs per row (75)
-constexpr int kLYTasks = 5 * kLCols;        // y passes per level (375)
-constexpr int kLX1 = 5 * kLRows * kLCols;   // x-modes of one level (12000 values)
+constexpr int kLThreads = kLX * kLRows;     // 256
+constexpr int kLCols = kLPX * 5;            // (patch column, x-mode) pairs per row (35)
+constexpr int kLYTasks = 5 * kLCols;        // y passes per level (175)
+constexpr int kLX1 = 5 * kLRows * kLCols;   // x-modes of one level (5600 values)
 
-// DPP row shifts (16-lane rows).  Lanes without a source get 0.
+// DPP row shifts (16-lane rows).  Lanes without a source get 0.  A 16-lane row
+// holds two lattice rows of 8 lanes; a shift that crosses from one to the
+// other only reaches lane 0 of a lattice row (shift up: its node 0 and its
+// window inputs, which lane 0 does not use) or takes lane 0's values into
+// lane 7 (shift down: lane 0 has no window, so its backward x-modes and its
+// node 0 are exact zeros, as a lane past the row would give).
 constexpr int kRowShr1 = 0x111;   // lane i takes lane i-1
 constexpr int kRowShl1 = 0x101;   // lane i takes lane i+1
 
@@ -162,7 +170,7 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
   const int C0 = tz * zlen, C1 = min(n, C0 + zlen);
 
   const int tid = threadIdx.x;
-  const int lam = tid & 15, m = tid >> 4;              // lane in the row, lattice row
+  const int lam = tid % kLX, m = tid / kLX;            // lane in the row, lattice row
   const int mu = (m + 1) / 3, iy = (m + 1) - 3 * ((m + 1) / 3);   // cell row in the tile, local y index
   const int cx = X0 - 1 + lam, cy = Y0 - 1 + mu;
   const bool in_x = cx <= n - 1;                       // cx >= 0 always

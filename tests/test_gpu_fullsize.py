@@ -164,16 +164,16 @@ def test_patch_inverse_tile_seams(gpu_lib, n):
     """Q3 at sizes that place the x-tile, y-tile and z-chunk seams of the
     blocked kernel differently (one tile; a tile exactly full; one patch more;
     a last tile that mostly overlaps the one before; a partial last tile;
-    tiles of 15 patches (14 cells) along x, 7 (6) along y in FP64 and 10 (9) in
-    FP32): sampled cells on and next to every seam against the oracle, and
-    bit-identical copies everywhere."""
+    tiles of 7 patches (6 cells) along x and 10 (9) along y): sampled cells on and
+    next to every seam against the oracle, and bit-identical copies everywhere."""
     fe = gpu_lib
     k = 3
     m = StructuredMesh(3, k, n)
     r = uniform(m.n_cellwise, seed=206)
     g = rng(207)
-    xs = sorted({c for c in (0, 1, 13, 14, 15, 16, 27, 28, 29, 30, 31, 32, 33, n - 2, n - 1) if 0 <= c < n})
-    ys = sorted({c for c in (0, 1, 5, 6, 7, 8, 9, 10, 12, 13, 17, 18, 19, 27, 28, n - 2, n - 1) if 0 <= c < n})
+    xs = sorted({c for c in (0, 1, 5, 6, 7, 11, 12, 13, 14, 15, 16, 27, 28, 29, 30, 31, 32, 33, n - 2, n - 1)
+                 if 0 <= c < n})
+    ys = sorted({c for c in (0, 1, 8, 9, 10, 17, 18, 19, 27, 28, n - 2, n - 1) if 0 <= c < n})
     cells = {x + n * (y + n * int(g.integers(0, n))) for x in xs for y in ys}
     cells |= {x + n * (y + n * z) for x in xs for y in (0, n - 1) for z in (0, n - 1)}
     cells = np.array(sorted(cells), dtype=np.int64)
