@@ -191,6 +191,8 @@ fe_status launch_rhs(const fe_problem* p, void* b, hipStream_t s);
 fe_status launch_axpby(int64_t n, double a, const void* x, double b, void* y, fe_dtype dt, hipStream_t s);
 // y = a x + b y, y FP64, x FP64 or FP32 (xdt)
 fe_status launch_axpby_x(int64_t n, double a, const void* x, fe_dtype xdt, double b, double* y, hipStream_t s);
+fe_status launch_cg_update(int64_t n, double rho, const double* pq, const double* p, const double* q, double* x,
+                           double* r, hipStream_t s);
 fe_status launch_cast(int64_t n, const void* src, fe_dtype st, void* dst, fe_dtype dtt, hipStream_t s);
 fe_status launch_fill(int64_t n, void* x, double v, fe_dtype dt, hipStream_t s);
 fe_status dot_async(const fe_problem* p, int64_t n, const void* a, const void* b, fe_dtype dt,

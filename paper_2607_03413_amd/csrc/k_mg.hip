@@ -227,6 +227,29 @@ __global__ void __launch_bounds__(256) k_axpby(int64_t n, T a, const T* __restri
   if (e < n) y[e] = b == T(0) ? a * x[e] : fma(a, x[e], b * y[e]);
 }
 
+// CG update with the step length formed on the device: alpha = rho / <p, A p>
+// read from device memory (no host round trip), x += alpha p, r -= alpha q.
+// A non-positive or non-finite <p, A p> leaves x and r as they are (the host
+// reports the breakdown after its next read).
+__global__ void __launch_bounds__(256) k_cg_update(int64_t n, double rho, const double* __restrict__ pq,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   double* __restrict__ x, double* __restrict__ r) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double d = *pq;
+  if (e >= n || !(d > 0.0) || !(d < INFINITY)) return;
+  const double alpha = rho / d;
+  x[e] = fma(alpha, p[e], x[e]);
+  r[e] = fma(-alpha, q[e], r[e]);
+}
+
+fe_status launch_cg_update(int64_t n, double rho, const double* pq, const double* p, const double* q, double* x,
+                           double* r, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, s, n, rho, pq, p, q, x, r);
+  FE_HIP_CHECK(hipGetLastError());
+  return FE_OK;
+}
+
 // y = a x + b y with an FP32 x (converted exactly) and FP64 y
 __global__ void __launch_bounds__(256) k_axpby_f32x(int64_t n, double a, const float* __restrict__ x, double b,
                                                     double* __restrict__ y) {

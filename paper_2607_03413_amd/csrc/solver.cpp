@@ -64,6 +64,13 @@ static bool same_setup(const fe_pcg_opts& a, const fe_pcg_opts& b) {
 
 static double* dev_scalar(fe_problem* p, int i) { return p->solver->dscal.as<double>() + i; }
 
+// device scalars 0..2 in one copy and one wait
+static fe_status read_scalars3(fe_problem* p, double* out, hipStream_t s) {
+  FE_HIP_CHECK(hipMemcpyAsync(out, dev_scalar(p, 0), 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  FE_HIP_CHECK(hipStreamSynchronize(s));
+  return FE_OK;
+}
+
 static fe_status read_scalar(fe_problem* p, int i, double* out, hipStream_t s) {
   FE_HIP_CHECK(hipMemcpyAsync(out, dev_scalar(p, i), sizeof(double), hipMemcpyDeviceToHost, s));
   FE_HIP_CHECK(hipStreamSynchronize(s));
@@ -516,23 +523,23 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
     while (result == FE_OK && it < o->maxit) {
       ++it;
       FE_CHECK(launch_apply(p, -1, pv, q, FE_F64, s));
-      double pq;
+      // <p, A p> stays on the device: the update forms alpha there, and the
+      // host reads it with the residual norm and <r_new, z_old> in one copy
       FE_CHECK(dot_async(p, n, pv, q, FE_F64, dev_scalar(p, 0), s));
-      FE_CHECK(read_scalar(p, 0, &pq, s));
+      FE_CHECK(launch_cg_update(n, rho, dev_scalar(p, 0), pv, q, x, r, s));
+      if (o->flexible) FE_CHECK(dot_async_x(p, n, (const double*)r, zc, zdt, dev_scalar(p, 2), s));
+      // the residual test needs one assembled norm per iteration; the energy
+      // test reads <r, z> that the next direction needs anyway
+      if (!energy_stop) FE_CHECK(assembled_norm2_async(p, -1, r, FE_F64, dev_scalar(p, 1), s));
+      double sc[3];
+      FE_CHECK(read_scalars3(p, sc, s));
+      const double pq = sc[0], rz_old = o->flexible ? sc[2] : 0.0;
       if (!(pq > 0.0) || !std::isfinite(pq)) {
         result = fail(FE_EBREAKDOWN, "<p, A p> <= 0");
         break;
       }
-      const double alpha = rho / pq;
-      FE_CHECK(launch_axpby(n, alpha, pv, 1.0, x, FE_F64, s));
-      FE_CHECK(launch_axpby(n, -alpha, q, 1.0, r, FE_F64, s));
-      double rz_old = 0.0;
-      if (o->flexible) FE_CHECK(dot_async_x(p, n, (const double*)r, zc, zdt, dev_scalar(p, 2), s));
       if (!energy_stop) {
-        // the residual test needs one assembled norm per iteration; the energy
-        // test reads <r, z> that the next direction needs anyway
-        FE_CHECK(assembled_norm2_async(p, -1, r, FE_F64, dev_scalar(p, 1), s));
-        FE_CHECK(read_scalar(p, 1, &rr2, s));
+        rr2 = sc[1];
         relres = std::sqrt(rr2) / nb;
         if (!std::isfinite(relres)) {
           result = fail(FE_EBREAKDOWN, "non-finite residual");
@@ -540,7 +547,6 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
         }
         if (relres <= o->tol) break;
       }
-      if (o->flexible) FE_CHECK(read_scalar(p, 2, &rz_old, s));
       FE_CHECK(precond());
       double rho_new;
       FE_CHECK(dot_async_x(p, n, (const double*)r, zc, zdt, dev_scalar(p, 0), s));
