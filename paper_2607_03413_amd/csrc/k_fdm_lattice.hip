@@ -46,10 +46,10 @@
 // the cell layers C0 .. C1-1 and computes level C1 for the upper planes of
 // layer C1-1 (and level C0's lower planes are the chunk below's).
 //
-// The next level's input rows are loaded into registers while the current
-// level computes, and waited for at the end of the level, before its stores
-// are issued (with one counter for loads and stores, a later wait for loads
-// would wait for the stores too); the stores are not waited for.
+// In FP64 the next level's input rows are loaded into registers while the
+// current level computes, and waited for at the end of the level, before its
+// stores are issued (with one counter for loads and stores, a later wait for
+// loads would wait for the stores too); the stores are not waited for.
 #include "fe_internal.h"
 #include "kernel_common.h"
 
@@ -222,16 +222,29 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     gather(a1, b1, p1);
   }
   // input of the level: (vz-1, iz 3), (vz, 0), (vz, 1), (vz, 2)
+  // FP64 loads the next level's rows during the current level (two blocks per
+  // compute unit, 234 VGPRs); FP32 loads a level's rows at its start and hides
+  // the wait behind more blocks instead (99 VGPRs, five blocks per compute
+  // unit: 64 against 70 us at 64^3).
+  constexpr bool PREFETCH = sizeof(T) == 8;
   Row4<T> ia[4], ib[4];
-  load_plane(C0 - 1, 3, ia[0], ib[0]);
-  load_plane(C0, 0, ia[1], ib[1]);
-  load_plane(C0, 1, ia[2], ib[2]);
-  load_plane(C0, 2, ia[3], ib[3]);
+  if (PREFETCH) {
+    load_plane(C0 - 1, 3, ia[0], ib[0]);
+    load_plane(C0, 0, ia[1], ib[1]);
+    load_plane(C0, 1, ia[2], ib[2]);
+    load_plane(C0, 2, ia[3], ib[3]);
+  }
   T co0[3] = {T(0), T(0), T(0)}, co1[3] = {T(0), T(0), T(0)};   // partial sums of planes 3vz-2, 3vz-1
 
   for (int vz = C0; vz <= C1; ++vz) {
     T p2[3], p3[3], p4[3];
     {
+      if (!PREFETCH) {
+        load_plane(vz - 1, 3, ia[0], ib[0]);
+        load_plane(vz, 0, ia[1], ib[1]);
+        load_plane(vz, 1, ia[2], ib[2]);
+        load_plane(vz, 2, ia[3], ib[3]);
+      }
       T s0[3], s1[3];
       gather(ia[0], ib[0], s0);
       gather(ia[1], ib[1], s1);
@@ -240,7 +253,7 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
       gather(ia[2], ib[2], p3);
       gather(ia[3], ib[3], p4);
     }
-    if (vz + 1 <= C1) {
+    if (PREFETCH && vz + 1 <= C1) {
       load_plane(vz, 3, ia[0], ib[0]);
       load_plane(vz + 1, 0, ia[1], ib[1]);
       load_plane(vz + 1, 1, ia[2], ib[2]);
@@ -353,7 +366,7 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     // The next level's rows have had the whole level to arrive: wait for them
     // here, before the stores, so that the wait at the next level's gather is
     // not also a wait for these stores.
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    if (PREFETCH) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     if (vz - 1 >= C0) {
       store_plane(vz - 1, 1, w1);
       store_plane(vz - 1, 2, w2);

@@ -526,7 +526,8 @@ fe_status pcg_solve(fe_problem* p, const void* b, void* x, const fe_pcg_opts* o,
       // <p, A p> stays on the device: the update forms alpha there, and the
       // host reads it with the residual norm and <r_new, z_old> in one copy
       FE_CHECK(dot_async(p, n, pv, q, FE_F64, dev_scalar(p, 0), s));
-      FE_CHECK(launch_cg_update(n, rho, dev_scalar(p, 0), pv, q, x, r, s));
+      FE_CHECK(launch_cg_update(n, rho, dev_scalar(p, 0), (const double*)pv, (const double*)q, (double*)x, (double*)r,
+                                s));
       if (o->flexible) FE_CHECK(dot_async_x(p, n, (const double*)r, zc, zdt, dev_scalar(p, 2), s));
       // the residual test needs one assembled norm per iteration; the energy
       // test reads <r, z> that the next direction needs anyway
