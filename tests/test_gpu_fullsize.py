@@ -143,8 +143,10 @@ def test_apply_full_size(gpu_lib, k, n):
     P.close()
 
 
-@pytest.mark.parametrize("k,n", [(3, 64), (7, 32)])
+@pytest.mark.parametrize("k,n", [(3, 64), (3, 96), (7, 32)])
 def test_patch_inverse_full_size(gpu_lib, k, n):
+    """Sampled cells at the benchmark sizes, and Q3 at 96^3 (several z chunks of
+    the lattice kernel per column of tiles, 16 x 11 tiles of 7 x 10 patches)."""
     fe = gpu_lib
     m = StructuredMesh(3, k, n)
     r = uniform(m.n_cellwise, seed=203)
