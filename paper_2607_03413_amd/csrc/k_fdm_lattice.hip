@@ -250,8 +250,8 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
   }
   // input of the level: (vz-1, iz 3), (vz, 0), (vz, 1), (vz, 2)
   // FP64 loads the next level's rows during the current level (two blocks per
-  // compute unit, 234 VGPRs); FP32 loads a level's rows at its start and hides
-  // the wait behind more blocks instead (99 VGPRs, four blocks per compute
+  // compute unit, 237 VGPRs); FP32 loads a level's rows at its start and hides
+  // the wait behind more blocks instead (102 VGPRs, four blocks per compute
   // unit: 64 against 70 us at 64^3).
   constexpr bool PREFETCH = sizeof(T) == 8;
   Row4<T> ia[4], ib[4];
