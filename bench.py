@@ -141,7 +141,8 @@ def source_digest(path):
 
 
 def kernel_bytes(P, dt_bytes):
-    """Algorithmic bytes per launch of each kernel family."""
+    """Algorithmic bytes per launch of each kernel family: every vector entry read once and
+    written once, plus the patch-solution scratch of the two-pass kernels."""
     k, n = P.degree, P.n
     n_patches = (n - 1) ** 3
     vec = P.len * dt_bytes
@@ -478,7 +479,7 @@ def cpu_baseline():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     import torch
