@@ -21,4 +21,9 @@ kron       Kronecker form of the Cartesian operator and its exact solver
 multigrid  assembled hierarchy, classical smoothers, V-cycle, PCG
 sepfit     averaged-geometry separable factors and the separable patch inverse
 learned    patch features, best-fit targets, reference MLP forward / manual backward / Adam step
+adaptive   refinement tree, level spaces, hanging-node constraints, classical local V-cycle
+multiblock multi-block atlas, its global numbering and inter-block DSS
+rhs        load vectors of the manufactured solution
+c_oracle   the Cartesian cell-wise apply and vertex-patch inverse as plain C (csrc/fe_oracle.c,
+           OpenMP over independent outputs), for the CPU baseline at full benchmark sizes
 """

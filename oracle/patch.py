@@ -78,13 +78,13 @@ def patch_inverse_global(A_csr, mesh, r_global, shared=False):
     return z
 
 
-def patch_inverse_cartesian(mesh, r_cell):
-    """z = G sum_p R_p^T A_p^{-1} R_p G^T r on a uniform Cartesian mesh of any size.
+def shared_patch_inverse(mesh):
+    """A_p^{-1} of every interior vertex patch of a uniform Cartesian mesh.
 
-    Every interior patch matrix is then the same (translation invariance; the
-    patch interiors never touch the boundary), so A_p is taken from the one
-    interior vertex of a 2^d mesh with the same element matrix, inverted once
-    (Cholesky) and applied to all patches as one dense product.
+    Every interior patch matrix is the same (translation invariance; the patch
+    interiors never touch the boundary), so A_p is taken from the one interior
+    vertex of a 2^d mesh with the same element matrix and inverted once
+    (Cholesky). Rows and columns in the patch's interior order, x fastest.
     """
     from .mesh import StructuredMesh
     from .operators import assemble_csr, element_matrix_cartesian
@@ -92,7 +92,15 @@ def patch_inverse_cartesian(mesh, r_cell):
     A_small = assemble_csr(small, element_matrix_cartesian(mesh.dim, mesh.k, mesh.h))
     i0 = patch_dof_indices(small)[0]
     Ap = A_small[i0][:, i0].toarray()
-    Ainv = sla.cho_solve(sla.cho_factor(Ap), np.eye(Ap.shape[0]))
+    return sla.cho_solve(sla.cho_factor(Ap), np.eye(Ap.shape[0]))
+
+
+def patch_inverse_cartesian(mesh, r_cell):
+    """z = G sum_p R_p^T A_p^{-1} R_p G^T r on a uniform Cartesian mesh of any size,
+    the shared A_p^{-1} (shared_patch_inverse) applied to all patches as one
+    dense product.
+    """
+    Ainv = shared_patch_inverse(mesh)
     idx = patch_dof_indices(mesh)
     r_global = mesh.assemble(r_cell)
     z = np.zeros_like(r_global)
