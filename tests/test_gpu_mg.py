@@ -237,5 +237,15 @@ def test_pcg_graph_replay_matches_eager(gpu_lib, smoother, inner, flexible, k, n
             it_g, x_g = solve(o)
             assert it_g == it_ref
             assert np.array_equal(x_g, x_ref)
+        # a V-cycle with an odd number of sweeps between two replayed solves (with
+        # Jacobi the levels' iterate and scratch buffers trade places): the next
+        # solve must not replay a graph captured on the old buffers
+        dt = torch.float64 if inner == 0 else torch.float32
+        e1 = P.cellvec(dt)
+        P.vcycle(b.to(dt), e1, fe.default_opts(smoother=smoother, inner=inner, flexible=flexible, nu_pre=1,
+                                               nu_post=2))
+        it_g, x_g = solve(opts)
+        assert it_g == it_e
+        assert np.array_equal(x_g, x_e)
     finally:
         fe.set_graphs(True)
