@@ -36,13 +36,32 @@ __global__ void __launch_bounds__(256) k_apply_cart3(const T* __restrict__ x, T*
   const int64_t cell = (int64_t)blockIdx.x * CPB + c;
   const bool active = cell < n_cells;
   int cx = 0, cy = 0, cz = 0;
-  if (active) cell_coords3<TPC % 64 == 0>(cell, n, cx, cy, cz);   // K = 8: one cell per wavefront
+  if (TPC % 64 == 0) {   // K = 8: one cell per wavefront, divisions on the scalar unit
+    if (active) cell_coords3<true>(cell, n, cx, cy, cz);
+  } else if (n >= CPB) {
+    // the block's first cell on the scalar unit, then at most one row wrap per cell
+    int bx, by, bz;
+    cell_coords3<true>((int64_t)blockIdx.x * CPB, n, bx, by, bz);
+    cx = bx + c;
+    cy = by;
+    cz = bz;
+    if (cx >= n) {
+      cx -= n;
+      if (++cy >= n) {
+        cy = 0;
+        ++cz;
+      }
+    }
+  } else if (active) {
+    cell_coords3<false>(cell, n, cx, cy, cz);
+  }
   T* la = sa + c * CS;
   T* lb = sb + c * CS;
 
-  // Dirichlet mask of z-pencil (ix = p0, iy = p1): bit iz set if masked
+  // Dirichlet mask of z-pencil (ix = p0, iy = p1): bit iz set if masked (only
+  // cells on the boundary of the cube have any)
   uint32_t zmask = 0;
-  if (dirichlet && active) {
+  if (dirichlet && active && (cx == 0 || cy == 0 || cz == 0 || cx == n - 1 || cy == n - 1 || cz == n - 1)) {
     const bool mxy = on_boundary(cx, p0, n, k) || on_boundary(cy, p1, n, k);
 #pragma unroll
     for (int iz = 0; iz < K; ++iz)
