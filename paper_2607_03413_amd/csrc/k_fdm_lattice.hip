@@ -280,12 +280,17 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
       gather(ia[2], ib[2], p3);
       gather(ia[3], ib[3], p4);
     }
+    // The level's loads and stores are issued at a raised wavefront priority,
+    // so that the other block's waves on the SIMD, in their compute phase, do
+    // not hold them back (FP64 at 64^3: 102 -> 100 us).
+    __builtin_amdgcn_s_setprio(3);
     if (PREFETCH && vz + 1 <= C1) {
       load_plane(vz, 3, ia[0], ib[0]);
       load_plane(vz + 1, 0, ia[1], ib[1]);
       load_plane(vz + 1, 1, ia[2], ib[2]);
       load_plane(vz + 1, 2, ia[3], ib[3]);
     }
+    __builtin_amdgcn_s_setprio(0);
     T E[3][3], O[3][2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -396,12 +401,14 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     // here, before the stores, so that the wait at the next level's gather is
     // not also a wait for these stores.
     if (PREFETCH) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __builtin_amdgcn_s_setprio(3);
     if (vz - 1 >= C0) {
       store_plane(vz - 1, 1, w1);
       store_plane(vz - 1, 2, w2);
       store_plane(vz - 1, 3, w3);
     }
     if (vz < C1) store_plane(vz, 0, w3);
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       p0[i] = p3[i];
