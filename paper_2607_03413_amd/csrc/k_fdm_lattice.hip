@@ -239,39 +239,47 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     nd[2] = v[2];
   };
 
-  // p[0], p[1]: planes 3vz-2, 3vz-1 of the current level (the previous level's upper planes)
+  // Chunks march alternately up (even tz) and down (odd tz): two neighbouring
+  // chunks reach the layers they both read at the same time (both at their
+  // first level, or both at their last), so that one of them finds them in
+  // L2.  Downward, the z window is taken in reverse (planes 3vz+2 .. 3vz-2):
+  // the even modes of a reversed window are the same and the odd modes
+  // exactly negated, so every plane comes out of the same additions as
+  // upward, bit for bit.
+  const bool down = (tz & 1) != 0;
+  const int lvl0 = down ? C1 : C0;
+  // p[0], p[1]: the first two planes of the window (upward 3vz-2, 3vz-1; downward
+  // 3vz+2, 3vz+1), carried from the level before
   T p0[3], p1[3];
   {
     Row4<T> a0, b0, a1, b1;
-    load_plane(C0 - 1, 1, a0, b0);
-    load_plane(C0 - 1, 2, a1, b1);
+    load_plane(down ? C1 : C0 - 1, down ? 2 : 1, a0, b0);
+    load_plane(down ? C1 : C0 - 1, down ? 1 : 2, a1, b1);
     gather(a0, b0, p0);
     gather(a1, b1, p1);
   }
-  // input of the level: (vz-1, iz 3), (vz, 0), (vz, 1), (vz, 2)
+  // input of the level: (vz-1, iz 3) and (vz, 0) (the vertex plane's copies),
+  // then upward (vz, 1), (vz, 2), downward (vz-1, 2), (vz-1, 1)
+  Row4<T> ia[4], ib[4];
+  auto load_level = [&](int vz) {
+    load_plane(vz - 1, 3, ia[0], ib[0]);
+    load_plane(vz, 0, ia[1], ib[1]);
+    load_plane(down ? vz - 1 : vz, down ? 2 : 1, ia[2], ib[2]);
+    load_plane(down ? vz - 1 : vz, down ? 1 : 2, ia[3], ib[3]);
+  };
   // FP64 loads the next level's rows during the current level (two blocks per
   // compute unit, 237 VGPRs); FP32 loads a level's rows at its start and hides
   // the wait behind more blocks instead (102 VGPRs, four blocks per compute
   // unit: 64 against 70 us at 64^3).
   constexpr bool PREFETCH = sizeof(T) == 8;
-  Row4<T> ia[4], ib[4];
-  if (PREFETCH) {
-    load_plane(C0 - 1, 3, ia[0], ib[0]);
-    load_plane(C0, 0, ia[1], ib[1]);
-    load_plane(C0, 1, ia[2], ib[2]);
-    load_plane(C0, 2, ia[3], ib[3]);
-  }
-  T co0[3] = {T(0), T(0), T(0)}, co1[3] = {T(0), T(0), T(0)};   // partial sums of planes 3vz-2, 3vz-1
+  if (PREFETCH) load_level(lvl0);
+  T co0[3] = {T(0), T(0), T(0)}, co1[3] = {T(0), T(0), T(0)};   // partial sums of the window's first two planes
 
-  for (int vz = C0; vz <= C1; ++vz) {
+  for (int step = 0; step <= C1 - C0; ++step) {
+    const int vz = down ? C1 - step : C0 + step;
     T p2[3], p3[3], p4[3];
     {
-      if (!PREFETCH) {
-        load_plane(vz - 1, 3, ia[0], ib[0]);
-        load_plane(vz, 0, ia[1], ib[1]);
-        load_plane(vz, 1, ia[2], ib[2]);
-        load_plane(vz, 2, ia[3], ib[3]);
-      }
+      if (!PREFETCH) load_level(vz);
       T s0[3], s1[3];
       gather(ia[0], ib[0], s0);
       gather(ia[1], ib[1], s1);
@@ -284,12 +292,7 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     // so that the other block's waves on the SIMD, in their compute phase, do
     // not hold them back (FP64 at 64^3: 102 -> 100 us).
     __builtin_amdgcn_s_setprio(3);
-    if (PREFETCH && vz + 1 <= C1) {
-      load_plane(vz, 3, ia[0], ib[0]);
-      load_plane(vz + 1, 0, ia[1], ib[1]);
-      load_plane(vz + 1, 1, ia[2], ib[2]);
-      load_plane(vz + 1, 2, ia[3], ib[3]);
-    }
+    if (PREFETCH && step + 1 <= C1 - C0) load_level(down ? vz - 1 : vz + 1);
     __builtin_amdgcn_s_setprio(0);
     T E[3][3], O[3][2];
 #pragma unroll
@@ -376,8 +379,9 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
       }
       __syncthreads();   // every row has read its x-modes before the next level writes them
     }
-    // the level's planes: 3vz-2 and 3vz-1 complete the partial sums of the level
-    // below, 3vz is the vertex plane (two copies), 3vz+1 and 3vz+2 start the next
+    // the level's planes (upward; downward mirrored): 3vz-2 and 3vz-1 complete the
+    // partial sums of the level before, 3vz is the vertex plane (two copies),
+    // 3vz+1 and 3vz+2 start the next
     T w1[3], w2[3], w3[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -402,11 +406,11 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     // not also a wait for these stores.
     if (PREFETCH) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     __builtin_amdgcn_s_setprio(3);
-    if (vz - 1 >= C0) {
-      store_plane(vz - 1, 1, w1);
-      store_plane(vz - 1, 2, w2);
-      store_plane(vz - 1, 3, w3);
+    if (down ? vz < C1 : vz - 1 >= C0) {   // the window's first two planes are in an owned layer
+      store_plane(down ? vz : vz - 1, down ? 2 : 1, w1);
+      store_plane(down ? vz : vz - 1, down ? 1 : 2, w2);
     }
+    if (vz - 1 >= C0) store_plane(vz - 1, 3, w3);
     if (vz < C1) store_plane(vz, 0, w3);
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
@@ -427,21 +431,24 @@ static fe_status lattice_typed(const fe_problem* p, int li, const T* r, T* z, co
   const int n = L.n;
   const int nxt = n <= kLPX + 1 ? 1 : (n - kLPX - 1 + kLPX - 2) / (kLPX - 1) + 1;
   const int nyt = n <= kLPY + 1 ? 1 : (n - kLPY - 1 + kLPY - 2) / (kLPY - 1) + 1;
-  static int resident = 0;
-  if (resident == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
     FE_HIP_CHECK(hipGetDevice(&dev));
     FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fdm_lattice3<T, true>, kLThreads, 0));
-    resident = cus * (per_cu > 0 ? per_cu : 1);
+    if (cus < 1) cus = 1;
   }
-  // z-chunk length that minimizes (rounds of blocks) x (levels per block)
+  // z-chunk length that minimizes (blocks per compute unit) x (levels per
+  // block): the blocks on a compute unit share its throughput, so this is the
+  // time of the most loaded unit; a unit with fewer than two blocks is counted
+  // as two, since one block alone cannot overlap its memory and compute
+  // phases (at 64^3 this picks 5 levels, the measured best in FP64 and FP32)
   const int64_t columns = (int64_t)nxt * nyt;
   int len = n;
   double best = 1e300;
   for (int l = 1; l <= n; ++l) {
     const int64_t blocks = columns * ((n + l - 1) / l);
-    const double cost = (double)((blocks + resident - 1) / resident) * (l + 1);
+    const double cost = (double)std::max<int64_t>((blocks + cus - 1) / cus, 2) * (l + 1);
     if (cost < best) { best = cost; len = l; }
   }
   const int64_t blocks = columns * ((n + len - 1) / len);
