@@ -45,8 +45,10 @@
 // X0+5 (the first also cell 0, the last everything up to n-1; the last tile
 // is shifted down so that it ends at patch n-1).  Along y, 10 patches and 9
 // cells.  Along z the mesh is cut into chunks of levels C0 .. C1; a chunk owns
-// the cell layers C0 .. C1-1 and computes level C1 for the upper planes of
-// layer C1-1 (and level C0's lower planes are the chunk below's).
+// the cell layers C0 .. C1-1 and computes the levels C0 .. C1 (level C1 for
+// the upper planes of layer C1-1; level C0's lower planes are the chunk
+// below's).  Even chunks march up, odd chunks down, so that two neighbouring
+// chunks read the layers they share at the same time (from L2 for the second).
 //
 // In FP64 the next level's input rows are loaded into registers while the
 // current level computes, and waited for at the end of the level, before its
