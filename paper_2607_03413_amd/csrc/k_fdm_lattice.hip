@@ -53,7 +53,10 @@
 // In FP64 the next level's input rows are loaded into registers while the
 // current level computes, and waited for at the end of the level, before its
 // stores are issued (with one counter for loads and stores, a later wait for
-// loads would wait for the stores too); the stores are not waited for.
+// loads would wait for the stores too); the stores are not waited for.  Rows
+// are loaded and stored through raw buffer resources over one plane of a cell
+// layer, so that lanes with nothing to load or store point past the range
+// (loads return zeros, stores are dropped) instead of branching: 3-7% at 64^3.
 #include "fe_internal.h"
 #include "kernel_common.h"
 
@@ -122,18 +125,32 @@ struct Row4 {
   T v[4];
 };
 template <typename T>
-__device__ __forceinline__ Row4<T> load_row(const T* __restrict__ p) {
+__device__ __forceinline__ Row4<T> load_row_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
   Row4<T> r;
   if constexpr (sizeof(T) == 8) {
     typedef double d2 __attribute__((ext_vector_type(2)));
-    const d2 a = *reinterpret_cast<const d2*>(p), b = *reinterpret_cast<const d2*>(p + 2);
+    const d2 a = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    const d2 b = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
     r.v[0] = a[0]; r.v[1] = a[1]; r.v[2] = b[0]; r.v[3] = b[1];
   } else {
     typedef float f4 __attribute__((ext_vector_type(4)));
-    const f4 a = *reinterpret_cast<const f4*>(p);
+    const f4 a = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
     r.v[0] = a[0]; r.v[1] = a[1]; r.v[2] = a[2]; r.v[3] = a[3];
   }
   return r;
+}
+template <typename T>
+__device__ __forceinline__ void store_row_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, T a, T b, T c, T d) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  if constexpr (sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, d2{a, b}), rs, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, d2{c, d}), rs, off + 16, 0, 0);
+  } else {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, f4{a, b, c, d}), rs, off, 0, 0);
+  }
 }
 template <typename T>
 __device__ __forceinline__ void store_row(T* __restrict__ p, T a, T b, T c, T d) {
@@ -223,13 +240,22 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
   }
 
   // input rows of one z-plane (own row and, in copy rows, row 3 of the cell row below)
+  // Rows are read through a raw buffer resource covering the plane (iz) of cell
+  // layer lz: a lane whose row lies outside the mesh points past the range
+  // (offset 2^31) and a layer outside the mesh gets an empty range, so that the
+  // buffer's range check returns the zeros, with no branch and no zero fill.
+  const uint32_t plane_bytes = (uint32_t)(plane * (int64_t)sizeof(T));
+  const uint32_t boff_row = ld_row ? (uint32_t)(row_off * (int64_t)sizeof(T)) : 0x80000000u;
+  const uint32_t boff_copy = ld_copy ? (uint32_t)(copy_off * (int64_t)sizeof(T)) : 0x80000000u;
+  const uint32_t soff_row = own_x && own_y ? (uint32_t)(row_off * (int64_t)sizeof(T)) : 0x80000000u;
+  const uint32_t soff_copy = own_x && own_yc ? (uint32_t)(copy_off * (int64_t)sizeof(T)) : 0x80000000u;
   auto load_plane = [&](int lz, int iz, Row4<T>& a, Row4<T>& b) {
-    const bool lz_ok = lz >= 0 && lz <= n - 1;
-    const int64_t zoff = (int64_t)lz * plane + iz * 16;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a.v[i] = b.v[i] = T(0);
-    if (lz_ok && ld_row) a = load_row(r + zoff + row_off);
-    if (lz_ok && ld_copy) b = load_row(r + zoff + copy_off);
+    const bool lz_ok = lz >= 0 && lz <= n - 1;   // uniform
+    const T* base = r + (int64_t)(lz_ok ? lz : 0) * plane + iz * 16;
+    const int nrec = lz_ok ? (int)(plane_bytes - (uint32_t)(iz * 16 * (int)sizeof(T))) : 0;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, nrec, 0x00020000);
+    a = load_row_buf<T>(rs, boff_row);
+    b = load_row_buf<T>(rs, boff_copy);
   };
   // the three own nodes of a loaded plane (x copies: local 3 of the lane below)
   auto gather = [&](const Row4<T>& a, const Row4<T>& b, T (&nd)[3]) {
@@ -396,8 +422,12 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     auto store_plane = [&](int lz, int iz, const T (&w)[3]) {
       const T w3x = dpp<kRowShl1>(w[0]);   // local 3: node 0 of the next cell
       const int64_t zoff = (int64_t)lz * plane + iz * 16;
-      if (own_x && own_y) store_row(z + zoff + row_off, w[0], w[1], w[2], w3x);
-      if (own_x && own_yc) store_row(z + zoff + copy_off, w[0], w[1], w[2], w3x);
+      // the owned row and copy row through a raw buffer resource over the plane:
+      // lanes that own neither point past its range and their writes are dropped
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          z + zoff, (short)0, (int)(plane_bytes - (uint32_t)(iz * 16 * (int)sizeof(T))), 0x00020000);
+      store_row_buf<T>(rs, soff_row, w[0], w[1], w[2], w3x);
+      store_row_buf<T>(rs, soff_copy, w[0], w[1], w[2], w3x);
       // domain boundary rows without a lattice row of their own: node rows 0 and 3n
       if (m == 0 && own_x && own_y && cy == 0) store_row(z + zoff + (row_off - 4), T(0), T(0), T(0), T(0));
       if (m == kLRows - 1 && own_x && own_y && cy == n - 1)
