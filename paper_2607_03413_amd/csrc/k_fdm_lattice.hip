@@ -296,9 +296,9 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     load_plane(down ? vz - 1 : vz, down ? 1 : 2, ia[3], ib[3]);
   };
   // FP64 loads the next level's rows during the current level (two blocks per
-  // compute unit, 237 VGPRs); FP32 loads a level's rows at its start and hides
-  // the wait behind more blocks instead (102 VGPRs, four blocks per compute
-  // unit: 64 against 70 us at 64^3).
+  // compute unit, 233 VGPRs); FP32 loads a level's rows at its start and hides
+  // the wait behind more blocks instead (94 VGPRs, five blocks per compute
+  // unit; prefetching measured 70 against 64 us at 64^3).
   constexpr bool PREFETCH = sizeof(T) == 8;
   if (PREFETCH) load_level(lvl0);
   T co0[3] = {T(0), T(0), T(0)}, co1[3] = {T(0), T(0), T(0)};   // partial sums of the window's first two planes
