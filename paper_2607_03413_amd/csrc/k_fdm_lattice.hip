@@ -239,11 +239,12 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
       }
   }
 
-  // input rows of one z-plane (own row and, in copy rows, row 3 of the cell row below)
-  // Rows are read through a raw buffer resource covering the plane (iz) of cell
+  // Input rows of one z-plane (own row and, in copy rows, row 3 of the cell row
+  // below), read through a raw buffer resource covering the plane (iz) of cell
   // layer lz: a lane whose row lies outside the mesh points past the range
-  // (offset 2^31) and a layer outside the mesh gets an empty range, so that the
-  // buffer's range check returns the zeros, with no branch and no zero fill.
+  // (offset 2^31, above any plane of n <= 2000) and a layer outside the mesh
+  // gets an empty range, so that the buffer's range check returns the zeros,
+  // with no branch and no zero fill; stores drop out-of-range writes alike.
   const uint32_t plane_bytes = (uint32_t)(plane * (int64_t)sizeof(T));
   const uint32_t boff_row = ld_row ? (uint32_t)(row_off * (int64_t)sizeof(T)) : 0x80000000u;
   const uint32_t boff_copy = ld_copy ? (uint32_t)(copy_off * (int64_t)sizeof(T)) : 0x80000000u;
@@ -461,6 +462,8 @@ template <typename T>
 static fe_status lattice_typed(const fe_problem* p, int li, const T* r, T* z, const T* coef, hipStream_t s) {
   const Level& L = p->levels[li];
   const int n = L.n;
+  // plane byte offsets fit the buffer resources' 31-bit ranges (n^2 64 8 < 2^31)
+  if (n > 2000) return fail(FE_EUNSUPPORTED, "lattice patch inverse: more than 2000 cells per axis");
   const int nxt = n <= kLPX + 1 ? 1 : (n - kLPX - 1 + kLPX - 2) / (kLPX - 1) + 1;
   const int nyt = n <= kLPY + 1 ? 1 : (n - kLPY - 1 + kLPY - 2) / (kLPY - 1) + 1;
   static int cus = 0;
