@@ -47,7 +47,7 @@ typedef enum {
   FE_EHIP = -3,         /* a HIP runtime call failed */
   FE_ENOTCONV = -4,     /* iteration limit reached; x holds the last iterate */
   FE_EBREAKDOWN = -5,   /* CG breakdown: <p, A p> <= 0 or <r, z> <= 0, or a non-finite value */
-  FE_EUNSUPPORTED = -6  /* valid request that this build does not implement */
+  FE_EUNSUPPORTED = -6  /* valid request that the library does not implement */
 } fe_status;
 
 typedef enum { FE_F64 = 0, FE_F32 = 1 } fe_dtype;
