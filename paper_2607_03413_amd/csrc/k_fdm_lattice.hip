@@ -171,7 +171,12 @@ __global__ void __launch_bounds__(kLThreads) __attribute__((amdgpu_waves_per_eu(
 k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
                                                             const T* __restrict__ Seo, const T* __restrict__ il,
                                                             int n, int nxt, int nyt, int zlen) {
-  __shared__ T X1[kLX1];   // [z-mode][lattice row][patch column][x-mode]
+  // [z-mode][lattice row][patch column][x-mode], then a zero window (read by the
+  // lanes of cell X0-1, which have no window of their own) and a window that the
+  // same lanes write and nobody reads: no lane-dependent branch around the LDS
+  // accesses of the x pass
+  __shared__ T X1[kLX1 + 16];
+  if (threadIdx.x < 16) X1[kLX1 + threadIdx.x] = T(0);   // ordered before its first read by the level's barriers
   const T* __restrict__ SE = Seo;
   const T* __restrict__ SO = Seo + 9;
 
@@ -297,8 +302,8 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     load_plane(down ? vz - 1 : vz, down ? 1 : 2, ia[3], ib[3]);
   };
   // FP64 loads the next level's rows during the current level (two blocks per
-  // compute unit, 233 VGPRs); FP32 loads a level's rows at its start and hides
-  // the wait behind more blocks instead (94 VGPRs, five blocks per compute
+  // compute unit, 201 VGPRs); FP32 loads a level's rows at its start and hides
+  // the wait behind more blocks instead (88 VGPRs, five blocks per compute
   // unit; prefetching measured 70 against 64 us at 64^3).
   constexpr bool PREFETCH = sizeof(T) == 8;
   if (PREFETCH) load_level(lvl0);
@@ -324,13 +329,14 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
     if (PREFETCH && step + 1 <= C1 - C0) load_level(down ? vz - 1 : vz + 1);
     __builtin_amdgcn_s_setprio(0);
     T E[3][3], O[3][2];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      E[i][0] = E[i][1] = E[i][2] = T(0);
-      O[i][0] = O[i][1] = T(0);
-    }
     const bool level_ok = vz >= 1 && vz <= n - 1;   // uniform over the block
-    if (level_ok) {
+    if (!level_ok) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        E[i][0] = E[i][1] = E[i][2] = T(0);
+        O[i][0] = O[i][1] = T(0);
+      }
+    } else {
       // z: the columns' 5 planes to the 5 z-modes
       T md[5][3];
 #pragma unroll
@@ -347,11 +353,9 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
         const T x[5] = {dpp<kRowShr1>(md[j][1]), dpp<kRowShr1>(md[j][2]), md[j][0], md[j][1], md[j][2]};
         T y[5];
         fwd5(x, y, SE, SO);
-        if (lam >= 1) {
-          T* dst = X1 + ((j * kLRows + m) * kLPX + px) * 5;
+        T* dst = lam >= 1 ? X1 + ((j * kLRows + m) * kLPX + px) * 5 : X1 + kLX1 + 8;
 #pragma unroll
-          for (int a = 0; a < 5; ++a) dst[a] = y[a];
-        }
+        for (int a = 0; a < 5; ++a) dst[a] = y[a];
       }
       __syncthreads();
       // y: one (z-mode, patch column, x-mode) per thread, all windows
@@ -386,19 +390,28 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
       // back along x, then accumulate the z back-transform of each mode
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
-        T y[5] = {T(0), T(0), T(0), T(0), T(0)}, w[5];
-        if (lam >= 1) {
-          const T* src = X1 + ((j * kLRows + m) * kLPX + px) * 5;
+        T y[5], w[5];
+        const T* src = lam >= 1 ? X1 + ((j * kLRows + m) * kLPX + px) * 5 : X1 + kLX1;
 #pragma unroll
-          for (int a = 0; a < 5; ++a) y[a] = src[a];
-        }
+        for (int a = 0; a < 5; ++a) y[a] = src[a];
         bwd5(y, w, SE, SO);
         const T v[3] = {w[2], w[3] + dpp<kRowShl1>(w[0]), w[4] + dpp<kRowShl1>(w[1])};
-        if (j < 3) {
+        // (the first even and the first odd mode start the accumulators)
+        if (j == 0) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) E[i][a] = SE[a] * v[i];
+        } else if (j < 3) {
 #pragma unroll
           for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int a = 0; a < 3; ++a) E[i][a] = fma(SE[3 * j + a], v[i], E[i][a]);
+        } else if (j == 3) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) O[i][a] = SO[a] * v[i];
         } else {
 #pragma unroll
           for (int i = 0; i < 3; ++i)
