@@ -304,7 +304,8 @@ k_fdm_lattice3(const T* __restrict__ r, T* __restrict__ z,
   // FP64 loads the next level's rows during the current level (two blocks per
   // compute unit, 201 VGPRs); FP32 loads a level's rows at its start and hides
   // the wait behind more blocks instead (88 VGPRs, five blocks per compute
-  // unit; prefetching measured 70 against 64 us at 64^3).
+  // unit; prefetching, at 111 VGPRs and four blocks, measured 59.1 against
+  // 58.1 us at 64^3, and six blocks at 80 VGPRs spill: 68.0 us).
   constexpr bool PREFETCH = sizeof(T) == 8;
   if (PREFETCH) load_level(lvl0);
   T co0[3] = {T(0), T(0), T(0)}, co1[3] = {T(0), T(0), T(0)};   // partial sums of the window's first two planes
