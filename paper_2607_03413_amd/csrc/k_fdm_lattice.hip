@@ -28,12 +28,15 @@
 //   * back along x (the window's 2 lower nodes go to the lane below) and z
 //     (the 2 upper planes are kept as partial sums for the next level).
 // The x-modes sit in LDS between the x and y passes (one array for the whole
-// level); all other values stay in registers.  A thread owns the nodes 0..2
+// level; the lanes of cell X0-1, which have no window, read a zero window and
+// write a discarded one, so that the x pass has no lane-dependent branch); all
+// other values stay in registers.  A thread owns the nodes 0..2
 // of one cell along x in one lattice row: 8 lanes are the cells X0-1 ..
 // X0+6 of a row, the 32 lattice rows make a 256-thread block.  Narrow tiles
 // keep the x-modes of a block at 45 KB (FP64), so that two blocks share a
 // compute unit and one's memory phase overlaps the other's compute (15
-// patches per row, one block per CU: 124 against 113 us FP64 at 64^3).
+// patches per row, one block per CU, measured 124 against 113 us FP64 at
+// 64^3 when the two shapes were compared).
 //
 // Every node is summed in a fixed order (lower window first along each axis;
 // in z the partial sums of the level below first), and every copy of a node
