@@ -116,6 +116,28 @@ def test_apply_fp64_and_fp32(gpu_lib, dim, k, n, bc):
         assert relerr(m.assemble(host(y)), A @ xg) < 1e-12
 
 
+@pytest.mark.parametrize("k,n", [(3, 15), (3, 16), (3, 17), (3, 23), (3, 33), (7, 5), (2, 17)])
+def test_apply_block_seams(gpu_lib, k, n):
+    """Sizes that place the apply's per-block cell runs across x-row boundaries
+    differently (Q3: 16 cells per pass, two passes per block in FP32; fewer cells
+    per row than per pass, exactly one row, one more, several rows and a ragged
+    last block), every entry against the dense per-cell oracle in both
+    precisions."""
+    fe = gpu_lib
+    m = StructuredMesh(3, k, n)
+    E = element_matrix_cartesian(3, k, m.h)
+    P = fe.Problem(3, k, n, bc=1)
+    x = m.gather(uniform(m.n_global, seed=108)).ravel()
+    expect = apply_dirichlet(m, E, x).ravel()
+    for dtype, tol, ent in ((torch.float64, 1e-12, 1e-11), (torch.float32, 1e-5, 1e-4)):
+        y = P.cellvec(dtype)
+        P.apply(dev(x, dtype), y)
+        got = host(y)
+        assert relerr(got, expect) < tol, (dtype, relerr(got, expect))
+        assert np.max(np.abs(got - expect)) <= ent * np.max(np.abs(expect)), dtype
+    P.close()
+
+
 @pytest.mark.parametrize("dim,k,n", [(2, 2, 16), (2, 3, 5), (3, 1, 4), (3, 2, 3), (3, 3, 4), (3, 3, 5),
                                      (3, 2, 9), (3, 3, 8), (3, 3, 1), (3, 4, 3), (3, 5, 3), (3, 6, 3),
                                      (3, 7, 3), (3, 8, 2)])
