@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256) k_amake_dinv(double* __restrict__ dinv, c
 }
 
 // ---------------------------------------------------------------- cell-wise updates
-// Raw per-copy Jacobi update (Algorithm 9, line 2): u = u + omega dinv (b - v),
+// Raw per-copy Jacobi update (the update step of Algorithm 9): u = u + omega dinv (b - v),
 // or u = omega dinv b from a zero iterate.
 __global__ void __launch_bounds__(256) k_ajacobi(double* __restrict__ u, const double* __restrict__ b,
                                                  const double* __restrict__ v, const double* __restrict__ dinv,
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) k_aprolong(const double* __restrict__ ec,
 
 // Algorithm 3 with the fused residual of Sec. 5 on a brick level:
 // bc(parent(b)) += sum_c (P_cx^T x P_cy^T x P_cz^T) (bf - vf)(8 b + c),
-// accumulating into the coarse level's right-hand side (Algorithm 5, line 7:
+// accumulating into the coarse level's right-hand side (Algorithm 5:
 // the coarse level already carries its own share of the active residual).
 template <int K>
 __global__ void __launch_bounds__(256) k_arestrict(const double* __restrict__ bf, const double* __restrict__ vf,

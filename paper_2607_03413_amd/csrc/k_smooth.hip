@@ -1,4 +1,4 @@
-// Fused masked Jacobi sweep of Algorithm 9 (lines 2 and 3 in one pass):
+// Fused masked Jacobi sweep of Algorithm 9 (its update and averaging steps in one pass):
 //   out = S_bar (u + omega Dhat^{-1} (b - v)),
 // Dhat^{-1} the valence-baked masked inverse diagonal (Sec. 5, eqs.
 // valence_baking and deferred_assembly).  One thread per cell-wise entry
