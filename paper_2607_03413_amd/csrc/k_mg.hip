@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(256) k_rhs_cart(double* __restrict__ b, const 
 }
 
 // Inverse diagonal with valence and Dirichlet mask baked in (Sec. 5,
-// eq. valence_baking and "constraints baked into the diagonal"):
+// eq. valence_baking, with the constraints folded into the diagonal):
 // dinv = kappa / d on interior copies, 0 on boundary copies.  d is the
 // assembled diagonal already gathered to every copy.
 template <typename T, int K, int DIM>

@@ -1,6 +1,6 @@
 """The paper's own experiments on the GPU path (Sec. 6.1 V-cycle convergence,
 Sec. 6.2 Table mg_solve_time): masked damped Jacobi multigrid, omega = 0.7,
-one pre- and one post-smoothing step ("2 smoothing steps"), FP64, on the unit
+one pre- and one post-smoothing step (two in all, the reading the paper's figures fit), FP64, on the unit
 cube, with the energy pairing of Sec. 3.4 (eq. energy_measure) as the
 convergence measure.  The paper's figures (tests/golden/paper_convergence.json)
 were taken at 128^3 cells on another GPU; here the same quantities are checked

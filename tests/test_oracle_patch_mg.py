@@ -143,9 +143,10 @@ def _contraction(h, M, A, cycles=12, seed=21):
 def test_jacobi_vcycle_contraction_against_paper():
     """Paper, Sec. 6.1: contraction 0.36 (p=2) to 0.49 (p=4) per V-cycle, omega = 0.7.
 
-    The paper's 'two smoothing steps' is read as nu1 = nu2 = 2; the contraction
-    of the classical V-cycle must then be no worse than the paper's figures and
-    must grow with p (a point smoother is not p-robust, Sec. 1).
+    The paper gives two smoothing steps per cycle; this check smooths twice
+    before and twice after (at least as much as any reading of that), so the
+    contraction of the classical V-cycle must be no worse than the paper's
+    figures, and it must grow with p (a point smoother is not p-robust, Sec. 1).
     """
     gold = json.load(open(GOLDEN))["vcycle_contraction_uniform"]
     rates = []
