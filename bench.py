@@ -10,7 +10,7 @@ events on the launch stream, the MG-PCG solves on Q7 32^3 (FP32 Chebyshev
 patch-FDM smoother inside FP64 CG vs the plain FP64 Jacobi-MG solve), and the
 CPU oracle timed on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-pcg] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 1000] [--no-pcg] [--no-cpu]
 """
 import argparse
 import itertools
@@ -34,7 +34,10 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    # untimed steps before the timed ones: the GPU needs about a tenth of a second
+    # of load to reach its steady clocks (Q3 64^3 FP64: 148 us per step after
+    # 10 warmup steps, 136 us after 1000 or when timing 1000 steps)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-deformed", action="store_true")
