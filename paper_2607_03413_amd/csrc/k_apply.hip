@@ -33,12 +33,134 @@ __device__ __forceinline__ void store_out(T v, T* p) {
   else *p = v;
 }
 
-// CPT > 1: a thread handles CPT cells of its block (cells c, c + CPB, ...):
-// the same per-cell work with CPT times the bytes in flight per wavefront,
-// which the FP32 Q3 apply needs to reach the memory rate (its cells are half
-// the bytes of FP64 ones for the same wavefront count).
-template <typename T, int K, int CPT = 1>
+template <typename T, int K>
 __global__ void __launch_bounds__(256) k_apply_cart3(const T* __restrict__ x, T* y,
+                                                     const T* __restrict__ Bm, const T* __restrict__ Dm,
+                                                     T scale, int n, int64_t n_cells, int dirichlet, T alpha,
+                                                     T beta, const T* bsrc) {
+  constexpr int TPC = K * K;
+  constexpr int CPB = 256 / TPC;
+  constexpr int RS = K + 1;
+  constexpr int PS = K * RS;
+  constexpr int CS = K * PS;
+  constexpr int k = K - 1;
+  __shared__ T sa[CPB * CS];
+  __shared__ T sb[CPB * CS];
+
+  const int tid = threadIdx.x;
+  const int c = tid / TPC;
+  const int p = tid - c * TPC;
+  const int p0 = p % K, p1 = p / K;
+  const int64_t cell = (int64_t)blockIdx.x * CPB + c;
+  const bool active = cell < n_cells;
+  int cx = 0, cy = 0, cz = 0;
+  if (TPC % 64 == 0) {   // K = 8: one cell per wavefront, divisions on the scalar unit
+    if (active) cell_coords3<true>(cell, n, cx, cy, cz);
+  } else if (n >= CPB) {
+    // the block's first cell on the scalar unit, then at most one row wrap per cell
+    int bx, by, bz;
+    cell_coords3<true>((int64_t)blockIdx.x * CPB, n, bx, by, bz);
+    cx = bx + c;
+    cy = by;
+    cz = bz;
+    if (cx >= n) {
+      cx -= n;
+      if (++cy >= n) {
+        cy = 0;
+        ++cz;
+      }
+    }
+  } else if (active) {
+    cell_coords3<false>(cell, n, cx, cy, cz);
+  }
+  T* la = sa + c * CS;
+  T* lb = sb + c * CS;
+
+  // Dirichlet mask of z-pencil (ix = p0, iy = p1): bit iz set if masked (only
+  // cells on the boundary of the cube have any)
+  uint32_t zmask = 0;
+  if (dirichlet && active && (cx == 0 || cy == 0 || cz == 0 || cx == n - 1 || cy == n - 1 || cz == n - 1)) {
+    const bool mxy = on_boundary(cx, p0, n, k) || on_boundary(cy, p1, n, k);
+#pragma unroll
+    for (int iz = 0; iz < K; ++iz)
+      if (mxy || on_boundary(cz, iz, n, k)) zmask |= 1u << iz;
+  }
+
+  T v[K], w[K], a[K], b[K];
+  // phase A: z-pencils, contraction along z
+  if (active) {
+    const T* xc = x + cell * (K * K * K) + p0 + K * p1;
+#pragma unroll
+    for (int iz = 0; iz < K; ++iz) v[iz] = load_in(xc + iz * K * K);
+#pragma unroll
+    for (int iz = 0; iz < K; ++iz)
+      if (zmask & (1u << iz)) v[iz] = T(0);
+  } else {
+#pragma unroll
+    for (int iz = 0; iz < K; ++iz) v[iz] = T(0);
+  }
+  pencil_mv<T, K>(Bm, v, a);
+  pencil_mv<T, K>(Dm, v, b);
+#pragma unroll
+  for (int iz = 0; iz < K; ++iz) {
+    la[iz * PS + p1 * RS + p0] = a[iz];
+    lb[iz * PS + p1 * RS + p0] = b[iz];
+  }
+  __syncthreads();
+
+  // phase B: y-pencils (ix = p0, iz = p1)
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    v[j] = la[p1 * PS + j * RS + p0];
+    w[j] = lb[p1 * PS + j * RS + p0];
+  }
+  pencil_mv<T, K>(Bm, v, a);            // c = B_y B_z x
+  pencil_mv2<T, K>(Dm, v, Bm, w, b);    // g = D_y B_z x + B_y D_z x
+  __syncthreads();
+#pragma unroll
+  for (int iy = 0; iy < K; ++iy) {
+    la[p1 * PS + iy * RS + p0] = a[iy];
+    lb[p1 * PS + iy * RS + p0] = b[iy];
+  }
+  __syncthreads();
+
+  // phase C: x-pencils (iy = p0, iz = p1)
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    v[j] = la[p1 * PS + p0 * RS + j];
+    w[j] = lb[p1 * PS + p0 * RS + j];
+  }
+  pencil_mv2<T, K>(Dm, v, Bm, w, a);    // D_x c + B_x g
+  __syncthreads();
+#pragma unroll
+  for (int ix = 0; ix < K; ++ix) la[p1 * PS + p0 * RS + ix] = a[ix] * scale;
+  __syncthreads();
+
+  // store through the z-pencil orientation (ix = p0, iy = p1), with the
+  // epilogue y = alpha A x + beta bsrc (read before y is written: bsrc may alias y)
+  if (active) {
+    const int64_t off = cell * (K * K * K) + p0 + K * p1;
+    T* yc = y + off;
+#pragma unroll
+    for (int iz = 0; iz < K; ++iz) {
+      T val = la[iz * PS + p1 * RS + p0];
+      if (zmask & (1u << iz)) val = T(0);
+      val *= alpha;
+      if (bsrc) val += beta * bsrc[off + iz * K * K];
+      store_out(val, yc + iz * K * K);
+    }
+  }
+}
+
+
+// The same operator with CPT cells per thread (cells c, c + CPB, ...): the same
+// per-cell work with CPT times the bytes in flight per wavefront, which the
+// FP32 Q3 apply needs to reach the memory rate (its cells are half the bytes
+// of FP64 ones for the same wavefront count).  A separate kernel: compiled with
+// one cell per thread it needs more scalar registers than the kernel above
+// (K = 6..9 FP64 spilled them to vector lanes).
+template <typename T, int K, int CPT>
+__global__ void __launch_bounds__(256) k_apply_cart3_multi(const T* __restrict__ x, T* y,
                                                      const T* __restrict__ Bm, const T* __restrict__ Dm,
                                                      T scale, int n, int64_t n_cells, int dirichlet, T alpha,
                                                      T beta, const T* bsrc) {
@@ -476,7 +598,7 @@ static fe_status apply_typed(const fe_problem* p, const Level& L, const T* x, T*
     constexpr int CPB = 256 / (K * K), CPT = 2;
     const int64_t nb = (L.n_cells + CPB * CPT - 1) / (CPB * CPT);
     ProfScope ps("apply", s);
-    hipLaunchKernelGGL((k_apply_cart3<T, K, CPT>), dim3((unsigned)nb), dim3(CPB * K * K), 0, s, x, y, Bm, Dm,
+    hipLaunchKernelGGL((k_apply_cart3_multi<T, K, CPT>), dim3((unsigned)nb), dim3(CPB * K * K), 0, s, x, y, Bm, Dm,
                        scale, L.n, L.n_cells, p->bc, alpha, beta, b);
   } else if (p->dim == 3) {
     constexpr int CPB = 256 / (K * K);
