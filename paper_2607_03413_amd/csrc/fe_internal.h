@@ -118,6 +118,7 @@ struct fe_problem {
   hipStream_t setup_stream = nullptr;
   fe::DeviceBuf coef64, coef32;      // 1D reference matrices (see Coef1D)
   fe::DeviceBuf geo_tab64, geo_tab32;  // deformed geometry: basis values/derivatives at Gauss points
+  fe::DeviceBuf geo_tabT64, geo_tabT32;  // their transposes PHI^T, DPHI^T (rows for the backward contractions)
   fe::Coef1D co;
   // host copies of the 1D data (FP64)
   std::vector<double> B, D, P0, P1, S, lam;

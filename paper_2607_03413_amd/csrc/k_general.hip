@@ -191,7 +191,8 @@ __global__ void k_convert_metric(const double* __restrict__ a, T* __restrict__ b
 template <typename T, int K, bool OTF = false>
 __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x, T* y,
                                                         const T* __restrict__ G, const T* __restrict__ PHI,
-                                                        const T* __restrict__ DPHI, int n, int64_t n_cells,
+                                                        const T* __restrict__ DPHI, const T* __restrict__ PHIT,
+                                                        const T* __restrict__ DPHIT, int n, int64_t n_cells,
                                                         int dirichlet, T alpha, T beta, const T* bsrc,
                                                         const double* __restrict__ geo = nullptr, double amp = 0.0) {
   constexpr int TPC = K * K;
@@ -317,9 +318,9 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
 #pragma unroll
     for (int q = 0; q < K; ++q) gx[q] = gy[q] = gz[q] = T(0);
   }
-  pencil_mtv<T, K>(DPHI, gx, a);   // s1 = DPHI_x^T fx
-  pencil_mtv<T, K>(PHI, gy, b);    // s_eta = PHI_x^T fy
-  pencil_mtv<T, K>(PHI, gz, w);    // s_zeta = PHI_x^T fz
+  pencil_mv<T, K>(DPHIT, gx, a);   // s1 = DPHI_x^T fx
+  pencil_mv<T, K>(PHIT, gy, b);    // s_eta = PHI_x^T fy
+  pencil_mv<T, K>(PHIT, gz, w);    // s_zeta = PHI_x^T fz
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < K; ++i) {
@@ -337,11 +338,11 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
   }
   {
     T t1[K], t2[K];
-    pencil_mtv<T, K>(PHI, v, t1);
-    pencil_mtv<T, K>(DPHI, w, t2);
+    pencil_mv<T, K>(PHIT, v, t1);
+    pencil_mv<T, K>(DPHIT, w, t2);
 #pragma unroll
     for (int i = 0; i < K; ++i) a[i] = t1[i] + t2[i];
-    pencil_mtv<T, K>(PHI, b, t1);
+    pencil_mv<T, K>(PHIT, b, t1);
 #pragma unroll
     for (int i = 0; i < K; ++i) b[i] = t1[i];
   }
@@ -354,8 +355,8 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
   for (int j = 0; j < K; ++j) { v[j] = l0[j * PS + p1 * RS + p0]; w[j] = l1[j * PS + p1 * RS + p0]; }
   {
     T t1[K], t2[K];
-    pencil_mtv<T, K>(PHI, v, t1);
-    pencil_mtv<T, K>(DPHI, w, t2);
+    pencil_mv<T, K>(PHIT, v, t1);
+    pencil_mv<T, K>(DPHIT, w, t2);
     if (active) {
       // epilogue y = alpha A x + beta bsrc (read before y is written: bsrc may alias y)
       const int64_t off = cell * K3 + p0 + K * p1;
@@ -365,7 +366,8 @@ __global__ void __launch_bounds__(256) k_apply_general3(const T* __restrict__ x,
         T val = (zmask & (1u << iz)) ? T(0) : t1[iz] + t2[iz];
         val *= alpha;
         if (bsrc) val += beta * bsrc[off + iz * K * K];
-        yc[iz * K * K] = val;
+        if constexpr (sizeof(T) == 8) __builtin_nontemporal_store(val, yc + iz * K * K);
+        else yc[iz * K * K] = val;
       }
     }
   }
@@ -503,14 +505,25 @@ static fe_status geometry_typed(fe_problem* p, hipStream_t s) {
                        L.metric64.as<double>(), L.metric32.as<float>(), nm6);
     FE_HIP_CHECK(hipGetLastError());
   }
-  // apply tables (PHI, DPHI) per dtype
-  std::vector<double> ap(2 * K * K);
+  // apply tables (PHI, DPHI) per dtype, and their transposes: the backward
+  // contractions (PHI^T v) read rows of PHI^T, fetched as whole rows by the
+  // scalar unit, instead of columns of PHI one value per scalar load (at K = 8
+  // FP64 that was 517 single loads and 300 scalar registers parked in vector
+  // lanes per cell pass)
+  std::vector<double> ap(2 * K * K), apt(2 * K * K);
   std::copy(tab.begin(), tab.begin() + 2 * K * K, ap.begin());
-  std::vector<float> ap32(ap.begin(), ap.end());
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < K; ++q)
+      for (int i = 0; i < K; ++i) apt[m * K * K + i * K + q] = ap[m * K * K + q * K + i];
+  std::vector<float> ap32(ap.begin(), ap.end()), apt32(apt.begin(), apt.end());
   FE_CHECK(p->geo_tab64.alloc(tab.size() * sizeof(double)));
   FE_CHECK(p->geo_tab32.alloc(ap32.size() * sizeof(float)));
+  FE_CHECK(p->geo_tabT64.alloc(apt.size() * sizeof(double)));
+  FE_CHECK(p->geo_tabT32.alloc(apt32.size() * sizeof(float)));
   FE_HIP_CHECK(hipMemcpyAsync(p->geo_tab64.p, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
   FE_HIP_CHECK(hipMemcpyAsync(p->geo_tab32.p, ap32.data(), ap32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  FE_HIP_CHECK(hipMemcpyAsync(p->geo_tabT64.p, apt.data(), apt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  FE_HIP_CHECK(hipMemcpyAsync(p->geo_tabT32.p, apt32.data(), apt32.size() * sizeof(float), hipMemcpyHostToDevice, s));
   FE_HIP_CHECK(hipStreamSynchronize(s));
   return FE_OK;
 }
@@ -522,19 +535,19 @@ fe_status setup_geometry(fe_problem* p, hipStream_t s) {
 
 template <typename T, int K>
 static fe_status apply_general_typed(const fe_problem* p, const Level& L, const T* x, T* y, const T* G,
-                                     const T* tab, T alpha, T beta, const T* b, hipStream_t s) {
+                                     const T* tab, const T* tabT, T alpha, T beta, const T* b, hipStream_t s) {
   constexpr int CPB = 256 / (K * K);
   const unsigned nb = (unsigned)((L.n_cells + CPB - 1) / CPB);
   if (p->metric_otf) {
     ProfScope ps("apply_general_otf", s);
     const T* kap = sizeof(T) == 8 ? (const T*)L.kappa64.p : (const T*)L.kappa32.p;
     hipLaunchKernelGGL((k_apply_general3<T, K, true>), dim3(nb), dim3(CPB * K * K), 0, s, x, y, kap, tab,
-                       tab + K * K, L.n, L.n_cells, p->bc, alpha, beta, b, p->geo_tab64.as<double>(),
+                       tab + K * K, tabT, tabT + K * K, L.n, L.n_cells, p->bc, alpha, beta, b, p->geo_tab64.as<double>(),
                        p->desc.deform_amp);
   } else {
     ProfScope ps("apply_general", s);
     hipLaunchKernelGGL((k_apply_general3<T, K, false>), dim3(nb), dim3(CPB * K * K), 0, s, x, y, G, tab,
-                       tab + K * K, L.n, L.n_cells, p->bc, alpha, beta, b, nullptr, 0.0);
+                       tab + K * K, tabT, tabT + K * K, L.n, L.n_cells, p->bc, alpha, beta, b, nullptr, 0.0);
   }
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
@@ -546,10 +559,12 @@ fe_status launch_apply_general(const fe_problem* p, int level, const void* x, vo
   if (dt == FE_F64) {
     FE_DISPATCH_K(p->K, return (apply_general_typed<double, KK>(p, L, (const double*)x, (double*)y,
                                                                 L.metric64.as<double>(), p->geo_tab64.as<double>(),
-                                                                alpha, beta, (const double*)b, s)));
+                                                                p->geo_tabT64.as<double>(), alpha, beta,
+                                                                (const double*)b, s)));
   }
   FE_DISPATCH_K(p->K, return (apply_general_typed<float, KK>(p, L, (const float*)x, (float*)y,
                                                              L.metric32.as<float>(), p->geo_tab32.as<float>(),
+                                                             p->geo_tabT32.as<float>(),
                                                              (float)alpha, (float)beta, (const float*)b, s)));
 }
 
