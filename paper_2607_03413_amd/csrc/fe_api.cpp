@@ -223,6 +223,16 @@ fe_status fe_problem_create(const fe_problem_desc* desc, void* stream, fe_proble
   p->co.off_P0 = put(p->P0);
   p->co.off_P1 = put(p->P1);
   {
+    std::vector<double> t0(p->P0.size()), t1(p->P1.size());
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) {
+        t0[i * K + j] = p->P0[j * K + i];
+        t1[i * K + j] = p->P1[j * K + i];
+      }
+    p->co.off_P0T = put(t0);
+    p->co.off_P1T = put(t1);
+  }
+  {
     // the patch kernel reads the eigenvalues right after S (M*M entries)
     std::vector<double> sl(p->S);
     sl.insert(sl.end(), p->lam.begin(), p->lam.end());

@@ -73,6 +73,7 @@ struct DeviceBuf {
 struct Coef1D {
   // offsets (in elements) into the buffer
   int off_B = 0, off_D = 0, off_P0 = 0, off_P1 = 0, off_diag = 0;
+  int off_P0T = 0, off_P1T = 0;  // transposes of P0, P1 (the restriction reads their rows)
   int off_S = 0, off_lam = 0;   // Cartesian patch eigen-data, scaled for h = 1
   // 3D Cartesian, k >= 2: even/odd halves of the 1D patch eigenvectors,
   // SE[(k)][k] then SO[(k-1)][k-1], then the M eigenvalues in that mode order

@@ -92,8 +92,8 @@ __global__ void __launch_bounds__(256) k_prolong3(const T* __restrict__ ec, T* _
 
 template <typename T, int K>
 __global__ void __launch_bounds__(256) k_restrict3(const T* __restrict__ bf, const T* __restrict__ vf,
-                                                   T* __restrict__ bc, const T* __restrict__ P0,
-                                                   const T* __restrict__ P1, int nc, int64_t n_parents) {
+                                                   T* __restrict__ bc, const T* __restrict__ P0T,
+                                                   const T* __restrict__ P1T, int nc, int64_t n_parents) {
   constexpr int TPC = K * K;
   constexpr int CPB = 256 / TPC;
   constexpr int RS = K + 1, PS = K * RS, CS = K * PS;
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(256) k_restrict3(const T* __restrict__ bf, con
 #pragma unroll
           for (int ix = 0; ix < K; ++ix) r[ix] = active ? bv[ix] : T(0);
         }
-        pencil_mtv<T, K>(bx ? P1 : P0, r, s);
+        pencil_mv<T, K>(bx ? P1T : P0T, r, s);
 #pragma unroll
         for (int i = 0; i < K; ++i) acc[i] += s[i];
       }
@@ -147,10 +147,10 @@ __global__ void __launch_bounds__(256) k_restrict3(const T* __restrict__ bf, con
       const T* s1 = sx + (CPB + c) * CS;
 #pragma unroll
       for (int j = 0; j < K; ++j) r[j] = s0[p1 * PS + j * RS + p0];
-      pencil_mtv<T, K>(P0, r, acc);
+      pencil_mv<T, K>(P0T, r, acc);
 #pragma unroll
       for (int j = 0; j < K; ++j) r[j] = s1[p1 * PS + j * RS + p0];
-      pencil_mtv<T, K>(P1, r, s);
+      pencil_mv<T, K>(P1T, r, s);
       T* dst = su + (bz * CPB + c) * CS;
 #pragma unroll
       for (int iy = 0; iy < K; ++iy) dst[p1 * PS + iy * RS + p0] = acc[iy] + s[iy];
@@ -162,10 +162,10 @@ __global__ void __launch_bounds__(256) k_restrict3(const T* __restrict__ bf, con
   const T* u1 = su + (CPB + c) * CS;
 #pragma unroll
   for (int j = 0; j < K; ++j) r[j] = u0[j * PS + p1 * RS + p0];
-  pencil_mtv<T, K>(P0, r, acc);
+  pencil_mv<T, K>(P0T, r, acc);
 #pragma unroll
   for (int j = 0; j < K; ++j) r[j] = u1[j * PS + p1 * RS + p0];
-  pencil_mtv<T, K>(P1, r, u);
+  pencil_mv<T, K>(P1T, r, u);
   if (active) {
     T* dst = bc + par * K3 + p0 + K * p1;
 #pragma unroll
@@ -428,8 +428,8 @@ static fe_status restrict_typed(const fe_problem* p, int fl, const T* bf, const 
   constexpr int CPB = 256 / (K * K);
   const unsigned nb = (unsigned)((C.n_cells + CPB - 1) / CPB);
   ProfScope ps("restrict", s);
-  hipLaunchKernelGGL((k_restrict3<T, K>), dim3(nb), dim3(CPB * K * K), 0, s, bf, vf, bc, coef + p->co.off_P0,
-                     coef + p->co.off_P1, C.n, C.n_cells);
+  hipLaunchKernelGGL((k_restrict3<T, K>), dim3(nb), dim3(CPB * K * K), 0, s, bf, vf, bc, coef + p->co.off_P0T,
+                     coef + p->co.off_P1T, C.n, C.n_cells);
   FE_HIP_CHECK(hipGetLastError());
   return FE_OK;
 }
