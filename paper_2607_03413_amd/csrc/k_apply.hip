@@ -152,7 +152,6 @@ __global__ void __launch_bounds__(256) k_apply_cart3(const T* __restrict__ x, T*
   }
 }
 
-
 // The same operator with CPT cells per thread (cells c, c + CPB, ...): the same
 // per-cell work with CPT times the bytes in flight per wavefront, which the
 // FP32 Q3 apply needs to reach the memory rate (its cells are half the bytes
@@ -594,12 +593,14 @@ static fe_status apply_typed(const fe_problem* p, const Level& L, const T* x, T*
                        (const float*)Bm, (const float*)Dm, (float)scale, L.n, L.n_cells, p->bc, (float)alpha,
                        (float)beta, (const float*)b);
   } else if (p->dim == 3 && K == 4 && sizeof(T) == 4) {
-    // FP32 Q3: two cells per thread (twice the bytes in flight)
-    constexpr int CPB = 256 / (K * K), CPT = 2;
-    const int64_t nb = (L.n_cells + CPB * CPT - 1) / (CPB * CPT);
-    ProfScope ps("apply", s);
-    hipLaunchKernelGGL((k_apply_cart3_multi<T, K, CPT>), dim3((unsigned)nb), dim3(CPB * K * K), 0, s, x, y, Bm, Dm,
-                       scale, L.n, L.n_cells, p->bc, alpha, beta, b);
+    if constexpr (K == 4 && sizeof(T) == 4) {   // (instantiated only here)
+      // FP32 Q3: two cells per thread (twice the bytes in flight)
+      constexpr int CPB = 256 / (K * K), CPT = 2;
+      const int64_t nb = (L.n_cells + CPB * CPT - 1) / (CPB * CPT);
+      ProfScope ps("apply", s);
+      hipLaunchKernelGGL((k_apply_cart3_multi<T, K, CPT>), dim3((unsigned)nb), dim3(CPB * K * K), 0, s, x, y, Bm,
+                         Dm, scale, L.n, L.n_cells, p->bc, alpha, beta, b);
+    }
   } else if (p->dim == 3) {
     constexpr int CPB = 256 / (K * K);
     const int64_t nb = (L.n_cells + CPB - 1) / CPB;
